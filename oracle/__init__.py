@@ -1,0 +1,17 @@
+"""Oracle for the gemm library: plain, slow, obviously correct CPU code.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the GPU library and never imports it; inputs reach it as numpy/torch CPU
+arrays produced by the seeded generators.
+
+Contents
+  gemm            FP64 C = alpha*A*B + beta*C0 (Tiramisu paper, Section I,
+                  the gemm problem statement) via liboracle.so (gemm_ref.c).
+  precision       bf16 / e4m3 rounding, the split-bf16x3 expected value and
+                  the per-tile quantiser (project precision forms; their
+                  readings are stated in each function).
+  normwise_error  ||X - R||_F / ||R||_F in FP64.
+"""
+from .gemm import gemm, gemm_rows, num_threads, normwise_error, lib_path  # noqa: F401
+from . import precision  # noqa: F401
