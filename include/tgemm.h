@@ -1,0 +1,185 @@
+/*
+ * tgemm — generalized matrix multiply for AMD MI355X (gfx950).
+ *
+ *     C = alpha * A * B + beta * C
+ *
+ * The operation is the gemm problem statement of the Tiramisu paper
+ * (Section I).  The kernels apply the transformations that paper lists for
+ * gemm: two-level tiling (Sections I and VI-A), array packing into a staging
+ * buffer (Section I; here the LDS), register blocking (Sections I and VI-A;
+ * here MFMA accumulator tiles), separation of full tiles from partial tiles
+ * (Section V-C, code generation: full tiles take an unpredicated body, partial
+ * tiles a predicated one, so no thread diverges), and tile sizes chosen by
+ * measurement (Section VI-A, autotuning).
+ *
+ * Conventions shared by every entry point
+ *   - Row-major storage, no transposes: A is M x K with row stride lda (in
+ *     elements), B is K x N with row stride ldb, C is M x N with row stride
+ *     ldc.  C is always float32.  The paper fixes none of this; it is the
+ *     reading this library takes.
+ *   - Matrix and scale pointers are DEVICE pointers owned by the caller; the
+ *     library keeps none of them after returning (except tgemm_batched, see
+ *     there).  Array arguments of tgemm_batched are HOST arrays.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Every call is stream-ordered and returns without synchronising.
+ *   - Arguments are validated on the host before any HIP call.  Degenerate
+ *     cases follow reference BLAS: M == 0 or N == 0 launches nothing;
+ *     K == 0 or alpha == 0 gives C = beta*C without reading A or B;
+ *     beta == 0 writes C without reading it (NaN/Inf in the old C vanish).
+ *   - Return value: a tgemm_status code.  Faults inside a kernel surface at
+ *     the caller's next synchronisation, not here.
+ *   - Calls are thread-safe; overlapping calls on one stream are ordered by
+ *     the stream, calls on different streams that write the same C race.
+ */
+#ifndef TGEMM_H
+#define TGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element type of A and B (C is always float32). */
+typedef enum {
+    TGEMM_F32 = 0,        /* float32 inputs, float32 MFMA                          */
+    TGEMM_F32_BF16X3 = 1, /* float32 inputs; each value split into hi = RNE_bf16(a)
+                             and lo = RNE_bf16(a - hi); the product is
+                             hi*hi + hi*lo + lo*hi on bf16 MFMA, float32 accumulate */
+    TGEMM_BF16 = 2,       /* bfloat16 inputs (uint16 bit patterns)                  */
+    TGEMM_FP8_E4M3 = 3    /* OCP E4M3FN bytes (largest finite 448)                  */
+} tgemm_dtype;
+
+typedef enum {
+    TGEMM_SUCCESS = 0,
+    TGEMM_INVALID_VALUE = 1,    /* bad size, leading dimension or null pointer     */
+    TGEMM_NOT_SUPPORTED = 2,    /* unknown dtype or schedule                       */
+    TGEMM_LAUNCH_FAILED = 3,    /* a HIP call or kernel launch returned an error   */
+    TGEMM_ALLOC_FAILED = 4,     /* device memory for a plan could not be allocated */
+    TGEMM_CAPTURE_UNPLANNED = 5,/* batched call under stream capture with no plan  */
+    TGEMM_INTERNAL = 6,
+    TGEMM_NO_DEVICE = 7         /* no usable gfx950 device                         */
+} tgemm_status;
+
+/*
+ * Single gemm: C = alpha*A*B + beta*C  (Tiramisu paper, Section I).
+ * dtype: TGEMM_F32 or TGEMM_F32_BF16X3 with float* A and B; TGEMM_BF16 or
+ * TGEMM_FP8_E4M3 with unscaled low-precision inputs (scale 1).
+ * Requires lda >= max(1,K), ldb >= max(1,N), ldc >= max(1,N).
+ * The tile schedule comes from the policy (tgemm_set_policy).
+ */
+int tgemm(int64_t M, int64_t N, int64_t K, float alpha,
+          const void* A, int64_t lda, const void* B, int64_t ldb,
+          float beta, float* C, int64_t ldc, int dtype, void* stream);
+
+/*
+ * Same as tgemm with an explicit schedule id (see tgemm_schedule_count /
+ * tgemm_schedule_info) and tile-order parameters: group_m >= 1 is the number
+ * of tile rows swept together, xcd_remap != 0 gives each XCD a contiguous
+ * run of tiles.  Used by the autotuner and by tests that must pin a schedule.
+ * Returns TGEMM_NOT_SUPPORTED if the schedule does not serve this dtype or
+ * this alignment (vectorised schedules need 16-byte aligned A/B bases and
+ * lda, ldb that are multiples of 4 elements).
+ */
+int tgemm_with_schedule(int64_t M, int64_t N, int64_t K, float alpha,
+                        const void* A, int64_t lda, const void* B, int64_t ldb,
+                        float beta, float* C, int64_t ldc, int dtype,
+                        int schedule_id, int group_m, int xcd_remap, void* stream);
+
+/*
+ * Scaled low-precision gemm (project addition; not in the paper):
+ *   C = alpha * sum_kb sA[i/128, kb] * sB[kb, j/128] * (sum_{k in kb} qA[i,k] qB[k,j])
+ *       + beta * C
+ * with one float32 scale per 128 x 128 tile of A (grid ceil(M/128) x
+ * ceil(K/128), row-major, row stride ceil(K/128)) and of B (grid
+ * ceil(K/128) x ceil(N/128), row stride ceil(N/128)); the last tiles may be
+ * partial.  dtype: TGEMM_BF16 (A, B are uint16 bf16 patterns) or
+ * TGEMM_FP8_E4M3 (A, B are bytes).  scaleA and scaleB are device pointers and
+ * must not be NULL when A and B are read.
+ */
+int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha,
+                 const void* A, int64_t lda, const float* scaleA,
+                 const void* B, int64_t ldb, const float* scaleB,
+                 float beta, float* C, int64_t ldc, int dtype, void* stream);
+
+/*
+ * Per-tile quantiser (project addition; not in the paper).  X is a rows x
+ * cols float32 row-major device matrix with row stride ldx.  For each
+ * 128 x 128 tile (the last ones partial): amax = max |x|;
+ *   TGEMM_FP8_E4M3: s = fl32(amax / 448) (s = 1 if amax == 0),
+ *                   q = round-to-nearest-even, saturating E4M3FN of fl32(x/s);
+ *   TGEMM_BF16:     s = 2^ceil(log2(amax)) (s = 1 if amax == 0),
+ *                   q = round-to-nearest-even bf16 of x/s.
+ * Q (device, element size 1 or 2 bytes, row stride ldq) and S (device,
+ * ceil(rows/128) x ceil(cols/128), row-major) are written.
+ */
+int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx,
+                         void* Q, int64_t ldq, float* S, int dtype, void* stream);
+
+/*
+ * Grouped gemm over `count` independent problems in one persistent launch
+ * (project addition).  Every array argument is a HOST array of length count;
+ * the matrix pointers in them are device pointers.  The first call for a new
+ * problem set (dimensions, leading dimensions, pointers, alpha, beta, dtype)
+ * chooses a schedule per problem, builds the tile index space and uploads a
+ * descriptor table to device memory owned by the library; later calls with
+ * the same set launch one kernel.  If `stream` is capturing and the set has
+ * no plan yet, the call returns TGEMM_CAPTURE_UNPLANNED: call once outside
+ * capture first.  dtype: TGEMM_F32 or TGEMM_F32_BF16X3.
+ */
+int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                  const float* alpha, const void* const* A, const int64_t* lda,
+                  const void* const* B, const int64_t* ldb, const float* beta,
+                  float* const* C, const int64_t* ldc, int dtype, void* stream);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* tgemm_status_string(int status);
+
+/*
+ * Schedule-selection policy for tgemm (Section VI-A: tile size found by
+ * measurement).  "default" (built-in rule), "tuned" (the tuning database,
+ * else default), "force:<id>" (one schedule id for every call it serves).
+ * Returns TGEMM_INVALID_VALUE for an unknown policy string.
+ */
+int tgemm_set_policy(const char* policy);
+
+/* Number of compiled schedules and the parameters of one of them.
+ * info receives 8 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes.
+ * Host-only: no HIP call. */
+int tgemm_schedule_count(void);
+int tgemm_schedule_info(int schedule_id, int* info);
+
+/*
+ * Tile placement of one launch, computed on the host exactly as the kernels
+ * compute it (no HIP call; used to check the tiling map of Section V-A is a
+ * bijection).  For workgroup w in [0, tiles_m*tiles_n) it writes tile_m[w],
+ * tile_n[w] and full[w] (1 when the tile lies inside M x N).
+ */
+int tgemm_tile_map(int64_t M, int64_t N, int BM, int BN, int group_m, int xcd_remap,
+                   int32_t* tile_m, int32_t* tile_n, int32_t* full);
+
+/*
+ * Measure every schedule that serves (M, N, K, dtype) on random device
+ * inputs the library allocates, median of `reps` timed launches each after
+ * warm-up, and append one JSON line per schedule to db_path (created if
+ * absent).  Schedules whose result differs from a fixed reference schedule
+ * on small-integer inputs are recorded as invalid.  Returns the best
+ * schedule id (>= 0) or a negative tgemm_status.
+ */
+int tgemm_autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps,
+                   const char* db_path);
+
+/* Load a tuning database (JSON lines) for the "tuned" policy. Host-only. */
+int tgemm_load_tuning_db(const char* db_path);
+
+/* Schedule the current policy would pick for a problem.  Host-only. */
+int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,
+                          int* schedule_id, int* group_m, int* xcd_remap);
+
+/* Frees plan caches and workspaces owned by the library. */
+void tgemm_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGEMM_H */

@@ -1,0 +1,26 @@
+// Compiled tile schedules: the compile-time part of a schedule (tile sizes,
+// wave grid, global-load width, precision mode).  The run-time part (tile
+// order: group_m and the XCD remap) is passed in GemmArgs.
+#pragma once
+#include "kargs.h"
+
+namespace tg {
+
+struct SchedDesc {
+    int dtype;      // tgemm_dtype this schedule serves
+    int BM, BN, BK; // macro-tile (level-1 tiling) and K panel
+    int WGM, WGN;   // wave grid: the macro-tile is split into WGM x WGN wave tiles
+    int vec;        // global load width in float32 elements (4 or 1)
+    int lds_bytes;  // LDS footprint (both stages)
+    int threads;
+    void (*kernel)(GemmArgs);
+};
+
+extern const SchedDesc kSchedules[];
+extern const int kNumSchedules;
+
+// Stream-ordered launches (defined in the HIP translation units).
+hipError_t launch_gemm(const SchedDesc& d, const GemmArgs& a, hipStream_t s);
+hipError_t launch_scale_c(int M, int N, float beta, float* C, int64_t ldc, hipStream_t s);
+
+}  // namespace tg

@@ -1,0 +1,188 @@
+// Schedule selection policies and the tuning database reader.
+#include "select.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "../../include/tgemm.h"
+#include "registry.h"
+
+namespace tg {
+
+namespace {
+
+enum Policy { POLICY_DEFAULT = 0, POLICY_TUNED = 1, POLICY_FORCE = 2 };
+
+struct TunedEntry {
+    Choice choice;
+    double ms;
+};
+
+std::mutex g_sel_mu;
+Policy g_policy = POLICY_DEFAULT;
+int g_force_id = -1;
+std::map<std::tuple<int, int64_t, int64_t, int64_t, int>, TunedEntry> g_tuned;  // (dtype,M,N,K,vec)
+
+bool json_number(const char* line, const char* key, double* out)
+{
+    char pat[64];
+    std::snprintf(pat, sizeof(pat), "\"%s\":", key);
+    const char* p = std::strstr(line, pat);
+    if (!p) return false;
+    p += std::strlen(pat);
+    while (*p == ' ') ++p;
+    char* end = nullptr;
+    const double v = std::strtod(p, &end);
+    if (end == p) return false;
+    *out = v;
+    return true;
+}
+
+bool json_true(const char* line, const char* key)
+{
+    char pat[64];
+    std::snprintf(pat, sizeof(pat), "\"%s\": true", key);
+    if (std::strstr(line, pat)) return true;
+    std::snprintf(pat, sizeof(pat), "\"%s\":true", key);
+    return std::strstr(line, pat) != nullptr;
+}
+
+}  // namespace
+
+int find_schedule(int dtype, int BM, int BN, int BK, int vec)
+{
+    for (int i = 0; i < kNumSchedules; ++i) {
+        const SchedDesc& d = kSchedules[i];
+        if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec) return i;
+    }
+    return -1;
+}
+
+int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
+{
+    (void)K;
+    const int vec = vec_allowed ? 4 : 1;
+    auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+    int id = -1;
+    if (dtype == TGEMM_F32) {
+        if (tiles(256, 128) >= 512) id = find_schedule(dtype, 256, 128, 16, vec);
+        else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, vec);
+        else id = find_schedule(dtype, 64, 64, 16, vec);
+    } else if (dtype == TGEMM_F32_BF16X3) {
+        if (tiles(256, 256) >= 512) id = find_schedule(dtype, 256, 256, 32, vec);
+        else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 32, vec);
+        else id = find_schedule(dtype, 64, 64, 32, vec);
+    }
+    if (id < 0) return TGEMM_NOT_SUPPORTED;
+    out->id = id;
+    out->group_m = 8;
+    out->xcd_remap = 1;
+    return TGEMM_SUCCESS;
+}
+
+int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
+{
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    if (g_policy == POLICY_FORCE) {
+        const int id = g_force_id;
+        if (id >= 0 && id < kNumSchedules && kSchedules[id].dtype == dtype &&
+            (kSchedules[id].vec == 1 || vec_allowed)) {
+            out->id = id;
+            out->group_m = 8;
+            out->xcd_remap = 1;
+            return TGEMM_SUCCESS;
+        }
+    } else if (g_policy == POLICY_TUNED) {
+        const int vec = vec_allowed ? 4 : 1;
+        auto it = g_tuned.find(std::make_tuple(dtype, M, N, K, vec));
+        if (it != g_tuned.end()) {
+            *out = it->second.choice;
+            return TGEMM_SUCCESS;
+        }
+    }
+    return default_schedule(M, N, K, dtype, vec_allowed, out);
+}
+
+}  // namespace tg
+
+extern "C" int tgemm_set_policy(const char* policy)
+{
+    using namespace tg;
+    if (!policy) return TGEMM_INVALID_VALUE;
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    if (std::strcmp(policy, "default") == 0) {
+        g_policy = POLICY_DEFAULT;
+    } else if (std::strcmp(policy, "tuned") == 0) {
+        g_policy = POLICY_TUNED;
+    } else if (std::strncmp(policy, "force:", 6) == 0) {
+        char* end = nullptr;
+        const long id = std::strtol(policy + 6, &end, 10);
+        if (end == policy + 6 || *end != '\0' || id < 0 || id >= kNumSchedules)
+            return TGEMM_INVALID_VALUE;
+        g_policy = POLICY_FORCE;
+        g_force_id = (int)id;
+    } else {
+        return TGEMM_INVALID_VALUE;
+    }
+    return TGEMM_SUCCESS;
+}
+
+// Reads JSON lines {"dtype":..,"M":..,"N":..,"K":..,"sched":..,"group_m":..,
+// "xcd":..,"ms":..,"valid":true}; keeps the fastest valid entry per problem.
+// Lines that do not parse are skipped.  Returns the number of entries used,
+// or a negative status when the file cannot be opened.
+extern "C" int tgemm_load_tuning_db(const char* db_path)
+{
+    using namespace tg;
+    if (!db_path) return -TGEMM_INVALID_VALUE;
+    FILE* f = std::fopen(db_path, "r");
+    if (!f) return -TGEMM_INVALID_VALUE;
+    char line[4096];
+    int used = 0;
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strchr(line, '\n') && !std::feof(f)) {  // overlong line: skip its rest
+            int c;
+            while ((c = std::fgetc(f)) != EOF && c != '\n') {}
+            continue;
+        }
+        double dt, m, n, k, id, gm, xcd, ms;
+        if (!json_number(line, "dtype", &dt) || !json_number(line, "M", &m) ||
+            !json_number(line, "N", &n) || !json_number(line, "K", &k) ||
+            !json_number(line, "sched", &id) || !json_number(line, "group_m", &gm) ||
+            !json_number(line, "xcd", &xcd) || !json_number(line, "ms", &ms))
+            continue;
+        if (!json_true(line, "valid")) continue;
+        const int sid = (int)id;
+        if (sid < 0 || sid >= kNumSchedules || kSchedules[sid].dtype != (int)dt) continue;
+        if (gm < 1 || gm > 64 || !(ms > 0)) continue;
+        const auto key = std::make_tuple((int)dt, (int64_t)m, (int64_t)n, (int64_t)k, kSchedules[sid].vec);
+        auto it = g_tuned.find(key);
+        if (it == g_tuned.end() || ms < it->second.ms) {
+            g_tuned[key] = TunedEntry{Choice{sid, (int)gm, xcd != 0 ? 1 : 0}, ms};
+        }
+        ++used;
+    }
+    std::fclose(f);
+    return used;
+}
+
+extern "C" int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype, int* schedule_id,
+                                     int* group_m, int* xcd_remap)
+{
+    using namespace tg;
+    if (!schedule_id || !group_m || !xcd_remap) return TGEMM_INVALID_VALUE;
+    if (M < 0 || N < 0 || K < 0) return TGEMM_INVALID_VALUE;
+    Choice c;
+    const int rc = select_schedule(M, N, K, dtype, true, &c);
+    if (rc != TGEMM_SUCCESS) return rc;
+    *schedule_id = c.id;
+    *group_m = c.group_m;
+    *xcd_remap = c.xcd_remap;
+    return TGEMM_SUCCESS;
+}

@@ -1,0 +1,25 @@
+// Schedule selection (Tiramisu paper, Section VI-A: tile sizes are chosen by
+// measurement on the target machine).  Policies: a built-in rule, the tuning
+// database written by the autotuner, or one forced schedule.
+#pragma once
+#include <stdint.h>
+
+namespace tg {
+
+struct Choice {
+    int id;
+    int group_m;
+    int xcd_remap;
+};
+
+// Picks a schedule for the current policy; vec_allowed says whether the
+// operands permit 16-byte loads.  Host-only.
+int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out);
+
+// Built-in rule only (also the fallback of the other policies).
+int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out);
+
+// Index of the compiled schedule with these parameters, or -1.
+int find_schedule(int dtype, int BM, int BN, int BK, int vec);
+
+}  // namespace tg

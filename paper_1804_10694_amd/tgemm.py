@@ -1,0 +1,245 @@
+"""Python binding of libtgemm.so (argument marshalling only).
+
+Every entry point has the name of the C function it calls (include/tgemm.h)
+without the `tgemm_` prefix.  Tensors are torch tensors on the GPU; the
+binding passes their data pointers, row strides and the current HIP stream.
+No arithmetic happens here, and there is no CPU fallback: if the library is
+not built, importing this module raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtgemm.so")
+
+F32, F32_BF16X3, BF16, FP8_E4M3 = 0, 1, 2, 3
+DTYPES = {"f32": F32, "x3": F32_BF16X3, "bf16": BF16, "fp8": FP8_E4M3}
+
+SUCCESS, INVALID_VALUE, NOT_SUPPORTED, LAUNCH_FAILED = 0, 1, 2, 3
+ALLOC_FAILED, CAPTURE_UNPLANNED, INTERNAL, NO_DEVICE = 4, 5, 6, 7
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+
+lib = ctypes.CDLL(LIB_PATH)
+_i64, _i32, _f32, _p = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_void_p
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pf32 = ctypes.POINTER(ctypes.c_float)
+_pp = ctypes.POINTER(ctypes.c_void_p)
+
+lib.tgemm.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _f32, _p, _i64, _i32, _p]
+lib.tgemm_with_schedule.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _f32, _p, _i64,
+                                    _i32, _i32, _i32, _i32, _p]
+lib.tgemm_scaled.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _p, _i64, _p, _f32, _p, _i64,
+                             _i32, _p]
+lib.tgemm_quantize_tiles.argtypes = [_i64, _i64, _p, _i64, _p, _i64, _p, _i32, _p]
+lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32, _pp,
+                              _pi64, _i32, _p]
+lib.tgemm_status_string.argtypes = [_i32]
+lib.tgemm_status_string.restype = ctypes.c_char_p
+lib.tgemm_set_policy.argtypes = [ctypes.c_char_p]
+lib.tgemm_schedule_count.argtypes = []
+lib.tgemm_schedule_info.argtypes = [_i32, _pi32]
+lib.tgemm_tile_map.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32, _pi32, _pi32, _pi32]
+lib.tgemm_autotune.argtypes = [_i64, _i64, _i64, _i32, _i32, ctypes.c_char_p]
+lib.tgemm_load_tuning_db.argtypes = [ctypes.c_char_p]
+lib.tgemm_select_schedule.argtypes = [_i64, _i64, _i64, _i32, _pi32, _pi32, _pi32]
+lib.tgemm_shutdown.argtypes = []
+lib.tgemm_shutdown.restype = None
+
+
+class TgemmError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}")
+
+
+def status_string(status):
+    return lib.tgemm_status_string(int(status)).decode()
+
+
+def _check(rc, where):
+    if rc != SUCCESS:
+        raise TgemmError(rc, where)
+    return rc
+
+
+def _dtype_code(dtype):
+    if isinstance(dtype, str):
+        return DTYPES[dtype]
+    return int(dtype)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+_ELEM = {F32: torch.float32, F32_BF16X3: torch.float32, BF16: torch.uint16, FP8_E4M3: torch.uint8}
+
+
+def _mat(t, name, elem=None):
+    """(data_ptr, leading dimension) of a row-major 2-D device tensor."""
+    if t is None:
+        return None, 1
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    if elem is not None and t.dtype != elem:
+        if not (elem == torch.uint16 and t.dtype in (torch.bfloat16, torch.int16)):
+            if not (elem == torch.uint8 and t.dtype in (torch.float8_e4m3fn, torch.int8)):
+                raise ValueError(f"{name} has dtype {t.dtype}, expected {elem}")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return t.data_ptr(), max(ld, 1)
+
+
+def gemm(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+    """C = alpha*A@B + beta*C in place (tgemm)."""
+    dt = _dtype_code(dtype)
+    M, K = A.shape
+    N = B.shape[1]
+    if B.shape[0] != K or tuple(C.shape) != (M, N):
+        raise ValueError(f"shape mismatch {tuple(A.shape)} @ {tuple(B.shape)} -> {tuple(C.shape)}")
+    pa, lda = _mat(A, "A", _ELEM.get(dt))
+    pb, ldb = _mat(B, "B", _ELEM.get(dt))
+    pc, ldc = _mat(C, "C", torch.float32)
+    _check(lib.tgemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dt, _stream_handle(stream)),
+           "tgemm")
+    return C
+
+
+def gemm_raw(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dtype, stream=None):
+    """tgemm on raw device pointers; returns the status code (no exception)."""
+    return lib.tgemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, _dtype_code(dtype),
+                     _stream_handle(stream) if stream is not False else None)
+
+
+def gemm_with_schedule(A, B, C, alpha, beta, dtype, schedule_id, group_m=8, xcd_remap=1,
+                       stream=None):
+    dt = _dtype_code(dtype)
+    M, K = A.shape
+    N = B.shape[1]
+    pa, lda = _mat(A, "A", _ELEM.get(dt))
+    pb, ldb = _mat(B, "B", _ELEM.get(dt))
+    pc, ldc = _mat(C, "C", torch.float32)
+    _check(lib.tgemm_with_schedule(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dt,
+                                   schedule_id, group_m, xcd_remap, _stream_handle(stream)),
+           "tgemm_with_schedule")
+    return C
+
+
+def gemm_scaled(A, sA, B, sB, C, alpha=1.0, beta=0.0, dtype="fp8", stream=None):
+    dt = _dtype_code(dtype)
+    M, K = A.shape
+    N = B.shape[1]
+    pa, lda = _mat(A, "A", _ELEM.get(dt))
+    pb, ldb = _mat(B, "B", _ELEM.get(dt))
+    pc, ldc = _mat(C, "C", torch.float32)
+    _check(lib.tgemm_scaled(M, N, K, alpha, pa, lda, sA.data_ptr(), pb, ldb, sB.data_ptr(), beta,
+                            pc, ldc, dt, _stream_handle(stream)), "tgemm_scaled")
+    return C
+
+
+def quantize_tiles(X, dtype="fp8", stream=None):
+    """(Q, S): per-128x128-tile quantised X and its scale grid (tgemm_quantize_tiles)."""
+    dt = _dtype_code(dtype)
+    rows, cols = X.shape
+    px, ldx = _mat(X, "X", torch.float32)
+    qdt = torch.uint8 if dt == FP8_E4M3 else torch.uint16
+    Q = torch.empty(rows, cols, dtype=qdt, device=X.device)
+    S = torch.empty(-(-rows // 128), -(-cols // 128), dtype=torch.float32, device=X.device)
+    _check(lib.tgemm_quantize_tiles(rows, cols, px, ldx, Q.data_ptr(), max(cols, 1), S.data_ptr(),
+                                    dt, _stream_handle(stream)), "tgemm_quantize_tiles")
+    return Q, S
+
+
+def _arr(ctype, values):
+    return (ctype * len(values))(*values)
+
+
+def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None):
+    """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p."""
+    dt = _dtype_code(dtype)
+    n = len(As)
+    Ms, Ns, Ks, pa, pb, pc, la, lb, lc = [], [], [], [], [], [], [], [], []
+    for A, B, C in zip(As, Bs, Cs):
+        M, K = A.shape
+        N = B.shape[1]
+        a, lda = _mat(A, "A", _ELEM.get(dt))
+        b, ldb = _mat(B, "B", _ELEM.get(dt))
+        c, ldc = _mat(C, "C", torch.float32)
+        Ms.append(M); Ns.append(N); Ks.append(K)
+        pa.append(a); pb.append(b); pc.append(c)
+        la.append(lda); lb.append(ldb); lc.append(ldc)
+    rc = lib.tgemm_batched(n, _arr(_i64, Ms), _arr(_i64, Ns), _arr(_i64, Ks),
+                           _arr(_f32, list(alphas)), _arr(_p, pa), _arr(_i64, la), _arr(_p, pb),
+                           _arr(_i64, lb), _arr(_f32, list(betas)), _arr(_p, pc), _arr(_i64, lc),
+                           dt, _stream_handle(stream))
+    _check(rc, "tgemm_batched")
+
+
+def set_policy(policy):
+    _check(lib.tgemm_set_policy(policy.encode()), "tgemm_set_policy")
+
+
+def schedule_count():
+    return lib.tgemm_schedule_count()
+
+
+def schedule_info(sid):
+    buf = (ctypes.c_int32 * 8)()
+    _check(lib.tgemm_schedule_info(sid, buf), "tgemm_schedule_info")
+    keys = ("dtype", "BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes")
+    return dict(zip(keys, list(buf)))
+
+
+def schedules(dtype=None):
+    out = []
+    for i in range(schedule_count()):
+        info = schedule_info(i)
+        if dtype is None or info["dtype"] == _dtype_code(dtype):
+            out.append((i, info))
+    return out
+
+
+def tile_map(M, N, BM, BN, group_m, xcd_remap):
+    T = (-(-M // BM)) * (-(-N // BN))
+    tm = (ctypes.c_int32 * T)()
+    tn = (ctypes.c_int32 * T)()
+    fl = (ctypes.c_int32 * T)()
+    _check(lib.tgemm_tile_map(M, N, BM, BN, group_m, xcd_remap, tm, tn, fl), "tgemm_tile_map")
+    return list(tm), list(tn), list(fl)
+
+
+def autotune(M, N, K, dtype, reps, db_path):
+    best = lib.tgemm_autotune(M, N, K, _dtype_code(dtype), reps, db_path.encode())
+    if best < 0:
+        raise TgemmError(-best, "tgemm_autotune")
+    return best
+
+
+def load_tuning_db(path):
+    n = lib.tgemm_load_tuning_db(path.encode())
+    if n < 0:
+        raise TgemmError(-n, "tgemm_load_tuning_db")
+    return n
+
+
+def select_schedule(M, N, K, dtype):
+    sid, gm, xcd = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.tgemm_select_schedule(M, N, K, _dtype_code(dtype), ctypes.byref(sid),
+                                     ctypes.byref(gm), ctypes.byref(xcd)), "tgemm_select_schedule")
+    return sid.value, gm.value, xcd.value
+
+
+def shutdown():
+    lib.tgemm_shutdown()
