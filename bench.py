@@ -1,0 +1,180 @@
+"""Benchmark of the gemm hot path on one MI355X.
+
+Workload (one "step"): C = alpha*A*B + beta*C with alpha = beta = 1 on seeded
+U[-1, 1] float32 inputs, for
+  - M = N = K = 8192 (seed 2), plain F32 and split-bf16x3;
+  - the ragged M = 4097, N = 3001, K = 2053 (seed 3, partial tiles), plain F32
+    and split-bf16x3.
+Inputs are resident in device memory before the timed region starts.  A step
+is the four launches, stream-ordered on torch's current stream; `value` is the
+step's algorithmic flops (2*M*N*K per gemm) divided by its wall time.  Every
+launch is also bracketed by HIP events, which give the per-path kernel time
+and the roofline of the dominant kernel.
+
+The cpu_baseline leg times the FP64 oracle on a bounded sample of rows of the
+8192^3 product (about ten seconds of host work) and reuses those rows to report
+the GPU paths' sampled normwise error.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "x3": 2516.6 / 3.0}   # MI355X dense: FP32 MFMA; bf16 MFMA / 3
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target host time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(A, B, C0, dev_results, seconds):
+    """Times the oracle on sampled rows of the 8192^3 problem; returns (baseline, errors)."""
+    import numpy as np
+    import oracle
+
+    M, K = A.shape
+    N = B.shape[1]
+    Bn = B.numpy()
+    rng = np.random.default_rng(2)
+    # calibration on a few rows, then a sample sized to the time budget
+    probe = np.sort(rng.choice(M, size=2 * oracle.num_threads(), replace=False))
+    t0 = time.perf_counter()
+    oracle.gemm_rows(A.numpy(), Bn, C0.numpy(), 1.0, 1.0, probe)
+    rows_per_s = len(probe) / (time.perf_counter() - t0)
+    nrows = int(max(8, min(M, seconds * rows_per_s)))
+    rows = np.sort(rng.choice(M, size=nrows, replace=False))
+    t0 = time.perf_counter()
+    ref = oracle.gemm_rows(A.numpy(), Bn, C0.numpy(), 1.0, 1.0, rows)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * nrows * N * K
+    base = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{nrows} of {M} rows of the 8192^3 F32 problem (FP64 i-k-j loop, "
+                      f"{dt:.1f} s, {flops:.3e} flops)"}
+    errors = {}
+    for name, C in dev_results.items():
+        errors[name] = oracle.normwise_error(C[rows], ref)
+    return base, errors
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1804_10694_amd import inputs
+    from paper_1804_10694_amd import tgemm as tg
+
+    dev = torch.device("cuda:0")
+    tg.set_policy("default")
+    sq = (8192, 8192, 8192)
+    rg = (4097, 3001, 2053)
+    host = {sq: inputs.gemm_inputs(*sq, seed=2), rg: inputs.gemm_inputs(*rg, seed=3)}
+    devm = {s: tuple(t.to(dev) for t in host[s]) for s in host}
+    C = {s: devm[s][2].clone() for s in host}
+    paths = [("f32", sq), ("x3", sq), ("f32", rg), ("x3", rg)]
+
+    def flops(shape):
+        return 2.0 * shape[0] * shape[1] * shape[2]
+
+    def launch(dt, s):
+        A, B, _ = devm[s]
+        tg.gemm(A, B, C[s], 1.0, 1.0, dt)
+
+    for _ in range(args.warmup):
+        for dt, s in paths:
+            launch(dt, s)
+    torch.cuda.synchronize()
+
+    ev = {p: [] for p in paths}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in paths:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            launch(*p)
+            e1.record()
+            ev[p].append((e0, e1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_flops = sum(flops(s) for _, s in paths)
+    value = step_flops / (ms_per_step * 1e-3) / 1e12
+
+    per_path = {}
+    for (dt, s), lst in ev.items():
+        times = sorted(a.elapsed_time(b) for a, b in lst)
+        avg = sum(times) / len(times)
+        med = times[len(times) // 2]
+        tf = flops(s) / (avg * 1e-3) / 1e12
+        per_path[f"{dt}_{s[0]}x{s[1]}x{s[2]}"] = {
+            "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(tf, 2),
+            "peak_tflops": round(PEAK_TFLOPS[dt], 1), "frac_peak": round(tf / PEAK_TFLOPS[dt], 4),
+            "schedule": tg.select_schedule(*s, dt)}
+
+    # dominant kernel = the path with the largest share of the step
+    dom_key = max(per_path, key=lambda k: per_path[k]["avg_ms"])
+    dom = per_path[dom_key]
+    roofline = {"bound": "mfma", "kernel": dom_key, "achieved": dom["tflops"],
+                "peak": dom["peak_tflops"], "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / dom["peak_tflops"], 4), "traffic": None}
+
+    # fresh results for the error report (outside the timed region)
+    results = {}
+    for dt, s in paths:
+        if s != sq:
+            continue
+        Cx = devm[s][2].clone()
+        A, B, _ = devm[s]
+        tg.gemm(A, B, Cx, 1.0, 1.0, dt)
+        torch.cuda.synchronize()
+        results[dt] = Cx.cpu().numpy()
+
+    base, errors = None, None
+    if not args.no_cpu_baseline:
+        base, errors = cpu_baseline(*host[sq], results, args.cpu_seconds)
+
+    x3 = per_path["x3_8192x8192x8192"]
+    f32 = per_path["f32_8192x8192x8192"]
+    out = {
+        "metric": "GEMM TFLOP/s & % peak: FP32 vs split-BF16x3 MFMA at <=1e-5 rel err; "
+                  "batched GEMM/s",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16x3(f32 accumulate)",
+        "data": "synthetic U[-1,1] float32, seeded",
+        "config": {"workload": "gemm C=AB+C, 8192^3 and 4097x3001x2053, plain F32 and "
+                               "split-bf16x3, one launch each per step", "alpha": 1.0,
+                   "beta": 1.0, "layout": "row-major", "parallelism": "single GPU"},
+        "paths": per_path,
+        "x3_over_f32": round(x3["tflops"] / f32["tflops"], 3),
+        "roofline": roofline,
+        "cpu_baseline": base,
+        "sampled_normwise_error_8192": errors,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
