@@ -204,3 +204,23 @@ def dequantize_e4m3(Q, S, tile=TILE):
 
 def dequantize_bf16(Q, S, tile=TILE):
     return dequantize_tiles(bf16_from_bits(Q).astype(np.float64), S, tile)
+
+
+# ----------------------------------------------------------- scaled gemm
+def decode(Q, dtype):
+    """float64 values of codes: dtype 'fp8' (E4M3FN bytes) or 'bf16' (16-bit patterns)."""
+    if dtype == "fp8":
+        return e4m3_decode(Q)
+    return bf16_from_bits(Q).astype(np.float64)
+
+
+def gemm_scaled_expected(QA, SA, QB, SB, C0, alpha, beta, dtype, tile=TILE):
+    """FP64 alpha * dequant(QA, SA) @ dequant(QB, SB) + beta * C0.
+
+    In exact arithmetic this equals the per-tile form
+    alpha * sum_kb SA[i/t, kb] SB[kb, j/t] sum_{k in kb} qA[i,k] qB[k,j] + beta*C0,
+    because every product qA*qB inside K block kb carries the same two scales.
+    """
+    Ad = dequantize_tiles(decode(QA, dtype), SA, tile)
+    Bd = dequantize_tiles(decode(QB, dtype), SB, tile)
+    return gemm(Ad, Bd, C0, alpha, beta)

@@ -84,8 +84,8 @@ bool vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int dtype)
 
 int schedule_serves(int id, int dtype, bool vec_allowed)
 {
-    if (id < 0 || id >= kNumSchedules) return TGEMM_NOT_SUPPORTED;
-    const SchedDesc& d = kSchedules[id];
+    if (id < 0 || id >= num_schedules()) return TGEMM_NOT_SUPPORTED;
+    const SchedDesc& d = schedule(id);
     if (d.dtype != dtype) return TGEMM_NOT_SUPPORTED;
     if (d.vec > 1 && !vec_allowed) return TGEMM_NOT_SUPPORTED;
     return TGEMM_SUCCESS;
@@ -115,11 +115,26 @@ GemmArgs make_args(const SchedDesc& d, int64_t M, int64_t N, int64_t K, float al
     return a;
 }
 
+int run_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+               const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
+               int64_t ldc, int dtype, int id, int group_m, int xcd_remap, hipStream_t s)
+{
+    const SchedDesc& d = schedule(id);
+    GemmArgs a = make_args(d, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap);
+    a.sA = sA;
+    a.sB = sB;
+    a.lds_a = (K + 127) / 128;
+    a.lds_b = (N + 127) / 128;
+    (void)dtype;
+    if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
+    return launch_gemm(d, a, s) == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+}
+
 int run_gemm(int id, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
              const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int group_m,
              int xcd_remap, hipStream_t stream)
 {
-    const SchedDesc& d = kSchedules[id];
+    const SchedDesc& d = schedule(id);
     GemmArgs a = make_args(d, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap);
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
     return launch_gemm(d, a, stream) == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
@@ -151,11 +166,6 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t l
     int rc = validate_gemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
     if (rc != TGEMM_SUCCESS) return rc;
     if (M == 0 || N == 0) return TGEMM_SUCCESS;
-    if (dtype != TGEMM_F32 && dtype != TGEMM_F32_BF16X3) {
-        // unscaled low precision runs as scale-1 tgemm_scaled
-        return tgemm_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc,
-                            dtype, stream);
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = ensure_device(s)) != TGEMM_SUCCESS) return rc;
     if (K == 0 || alpha == 0.f)
@@ -164,6 +174,9 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t l
     Choice ch;
     rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch);
     if (rc != TGEMM_SUCCESS) return rc;
+    if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)  // unscaled: every scale is 1
+        return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype,
+                          ch.id, ch.group_m, ch.xcd_remap, s);
     return run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m, ch.xcd_remap, s);
 }
 
@@ -183,15 +196,58 @@ int tgemm_with_schedule(int64_t M, int64_t N, int64_t K, float alpha, const void
     if (!reads_ab)
         return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
                                                                              : TGEMM_LAUNCH_FAILED;
+    if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)
+        return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype,
+                          schedule_id, group_m, xcd_remap, s);
     return run_gemm(schedule_id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap, s);
 }
 
-int tgemm_schedule_count(void) { return kNumSchedules; }
+int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+                 const float* scaleA, const void* B, int64_t ldb, const float* scaleB, float beta,
+                 float* C, int64_t ldc, int dtype, void* stream)
+{
+    if (dtype != TGEMM_BF16 && dtype != TGEMM_FP8_E4M3) return TGEMM_NOT_SUPPORTED;
+    int rc = validate_gemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (rc != TGEMM_SUCCESS) return rc;
+    if (M == 0 || N == 0) return TGEMM_SUCCESS;
+    const bool reads_ab = (K > 0 && alpha != 0.f);
+    if (reads_ab && (!scaleA || !scaleB)) return TGEMM_INVALID_VALUE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = ensure_device(s)) != TGEMM_SUCCESS) return rc;
+    if (!reads_ab)
+        return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
+                                                                             : TGEMM_LAUNCH_FAILED;
+    Choice ch;
+    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch);
+    if (rc != TGEMM_SUCCESS) return rc;
+    return run_scaled(M, N, K, alpha, A, lda, scaleA, B, ldb, scaleB, beta, C, ldc, dtype, ch.id,
+                      ch.group_m, ch.xcd_remap, s);
+}
+
+int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx, void* Q,
+                         int64_t ldq, float* S, int dtype, void* stream)
+{
+    if (dtype != TGEMM_BF16 && dtype != TGEMM_FP8_E4M3) return TGEMM_NOT_SUPPORTED;
+    if (rows < 0 || cols < 0 || rows > INT32_MAX || cols > INT32_MAX) return TGEMM_INVALID_VALUE;
+    if (ldx < (cols > 1 ? cols : 1) || ldq < (cols > 1 ? cols : 1)) return TGEMM_INVALID_VALUE;
+    if (rows == 0 || cols == 0) return TGEMM_SUCCESS;
+    if (!X || !Q || !S) return TGEMM_INVALID_VALUE;
+    const int64_t tiles = ((rows + 127) / 128) * ((cols + 127) / 128);
+    if (tiles > INT32_MAX) return TGEMM_INVALID_VALUE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = ensure_device(s);
+    if (rc != TGEMM_SUCCESS) return rc;
+    return launch_quantize((int)rows, (int)cols, X, ldx, Q, ldq, S, dtype, s) == hipSuccess
+               ? TGEMM_SUCCESS
+               : TGEMM_LAUNCH_FAILED;
+}
+
+int tgemm_schedule_count(void) { return num_schedules(); }
 
 int tgemm_schedule_info(int id, int* info)
 {
-    if (id < 0 || id >= kNumSchedules || !info) return TGEMM_INVALID_VALUE;
-    const SchedDesc& d = kSchedules[id];
+    if (id < 0 || id >= num_schedules() || !info) return TGEMM_INVALID_VALUE;
+    const SchedDesc& d = schedule(id);
     info[0] = d.dtype;
     info[1] = d.BM;
     info[2] = d.BN;

@@ -382,7 +382,7 @@ hipError_t launch_gemm(const SchedDesc& d, const GemmArgs& a, hipStream_t s)
 #define TG_SCHED_V(DT, MODE, BM, BN, BK, WGM, WGN) \
     TG_SCHED(DT, MODE, BM, BN, BK, WGM, WGN, 4), TG_SCHED(DT, MODE, BM, BN, BK, WGM, WGN, 1)
 
-const SchedDesc kSchedules[] = {
+static const SchedDesc kTileSchedules[] = {
     // plain float32 on v_mfma_f32_32x32x2_f32
     TG_SCHED_V(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2),
     TG_SCHED_V(TGEMM_F32, MODE_F32, 128, 128, 32, 2, 2),
@@ -398,6 +398,10 @@ const SchedDesc kSchedules[] = {
     TG_SCHED_V(TGEMM_F32_BF16X3, MODE_X3, 64, 64, 32, 2, 2),
     TG_SCHED_V(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 64, 2, 2),
 };
-const int kNumSchedules = sizeof(kSchedules) / sizeof(kSchedules[0]);
+const SchedDesc* tile_schedules(int* n)
+{
+    *n = (int)(sizeof(kTileSchedules) / sizeof(kTileSchedules[0]));
+    return kTileSchedules;
+}
 
 }  // namespace tg

@@ -4,17 +4,6 @@
 
 extern "C" {
 
-int tgemm_scaled(int64_t, int64_t, int64_t, float, const void*, int64_t, const float*, const void*,
-                 int64_t, const float*, float, float*, int64_t, int, void*)
-{
-    return TGEMM_NOT_SUPPORTED;
-}
-
-int tgemm_quantize_tiles(int64_t, int64_t, const float*, int64_t, void*, int64_t, float*, int, void*)
-{
-    return TGEMM_NOT_SUPPORTED;
-}
-
 int tgemm_batched(int64_t, const int64_t*, const int64_t*, const int64_t*, const float*,
                   const void* const*, const int64_t*, const void* const*, const int64_t*,
                   const float*, float* const*, const int64_t*, int, void*)

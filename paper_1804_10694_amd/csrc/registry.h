@@ -16,11 +16,19 @@ struct SchedDesc {
     void (*kernel)(GemmArgs);
 };
 
-extern const SchedDesc kSchedules[];
-extern const int kNumSchedules;
+// All compiled schedules, ids 0..num_schedules()-1 (tables of every kernel
+// translation unit, concatenated in a fixed order).
+int num_schedules();
+const SchedDesc& schedule(int id);
+
+// Per-translation-unit tables.
+const SchedDesc* tile_schedules(int* n);    // F32 and split-bf16x3
+const SchedDesc* scaled_schedules(int* n);  // bf16 and fp8 with per-tile scales
 
 // Stream-ordered launches (defined in the HIP translation units).
 hipError_t launch_gemm(const SchedDesc& d, const GemmArgs& a, hipStream_t s);
 hipError_t launch_scale_c(int M, int N, float beta, float* C, int64_t ldc, hipStream_t s);
+hipError_t launch_quantize(int rows, int cols, const float* X, int64_t ldx, void* Q, int64_t ldq,
+                           float* S, int dtype, hipStream_t s);
 
 }  // namespace tg

@@ -56,8 +56,8 @@ bool json_true(const char* line, const char* key)
 
 int find_schedule(int dtype, int BM, int BN, int BK, int vec)
 {
-    for (int i = 0; i < kNumSchedules; ++i) {
-        const SchedDesc& d = kSchedules[i];
+    for (int i = 0; i < num_schedules(); ++i) {
+        const SchedDesc& d = schedule(i);
         if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec) return i;
     }
     return -1;
@@ -77,6 +77,13 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     } else if (dtype == TGEMM_F32_BF16X3) {
         if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 32, vec);
         else id = find_schedule(dtype, 64, 64, 32, vec);
+    } else if (dtype == TGEMM_BF16) {
+        if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, vec);
+        else id = find_schedule(dtype, 64, 64, 64, vec);
+    } else if (dtype == TGEMM_FP8_E4M3) {
+        if (tiles(256, 128) >= 512) id = find_schedule(dtype, 256, 128, 128, vec);
+        else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 128, vec);
+        else id = find_schedule(dtype, 64, 128, 128, vec);
     }
     if (id < 0) return TGEMM_NOT_SUPPORTED;
     out->id = id;
@@ -90,8 +97,8 @@ int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed
     std::lock_guard<std::mutex> lk(g_sel_mu);
     if (g_policy == POLICY_FORCE) {
         const int id = g_force_id;
-        if (id >= 0 && id < kNumSchedules && kSchedules[id].dtype == dtype &&
-            (kSchedules[id].vec == 1 || vec_allowed)) {
+        if (id >= 0 && id < num_schedules() && schedule(id).dtype == dtype &&
+            (schedule(id).vec == 1 || vec_allowed)) {
             out->id = id;
             out->group_m = 8;
             out->xcd_remap = 1;
@@ -122,7 +129,7 @@ extern "C" int tgemm_set_policy(const char* policy)
     } else if (std::strncmp(policy, "force:", 6) == 0) {
         char* end = nullptr;
         const long id = std::strtol(policy + 6, &end, 10);
-        if (end == policy + 6 || *end != '\0' || id < 0 || id >= kNumSchedules)
+        if (end == policy + 6 || *end != '\0' || id < 0 || id >= num_schedules())
             return TGEMM_INVALID_VALUE;
         g_policy = POLICY_FORCE;
         g_force_id = (int)id;
@@ -159,9 +166,9 @@ extern "C" int tgemm_load_tuning_db(const char* db_path)
             continue;
         if (!json_true(line, "valid")) continue;
         const int sid = (int)id;
-        if (sid < 0 || sid >= kNumSchedules || kSchedules[sid].dtype != (int)dt) continue;
+        if (sid < 0 || sid >= num_schedules() || schedule(sid).dtype != (int)dt) continue;
         if (gm < 1 || gm > 64 || !(ms > 0)) continue;
-        const auto key = std::make_tuple((int)dt, (int64_t)m, (int64_t)n, (int64_t)k, kSchedules[sid].vec);
+        const auto key = std::make_tuple((int)dt, (int64_t)m, (int64_t)n, (int64_t)k, schedule(sid).vec);
         auto it = g_tuned.find(key);
         if (it == g_tuned.end() || ms < it->second.ms) {
             g_tuned[key] = TunedEntry{Choice{sid, (int)gm, xcd != 0 ? 1 : 0}, ms};

@@ -154,7 +154,7 @@ def quantize_tiles(X, dtype="fp8", stream=None):
     dt = _dtype_code(dtype)
     rows, cols = X.shape
     px, ldx = _mat(X, "X", torch.float32)
-    qdt = torch.uint8 if dt == FP8_E4M3 else torch.uint16
+    qdt = torch.uint8 if dt == FP8_E4M3 else torch.int16   # bf16 bit patterns
     Q = torch.empty(rows, cols, dtype=qdt, device=X.device)
     S = torch.empty(-(-rows // 128), -(-cols // 128), dtype=torch.float32, device=X.device)
     _check(lib.tgemm_quantize_tiles(rows, cols, px, ldx, Q.data_ptr(), max(cols, 1), S.data_ptr(),

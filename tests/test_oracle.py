@@ -266,3 +266,25 @@ def test_lowprec_outlier_rows():
     big_a = (A.abs().max(dim=1).values > 100).sum().item()
     big_b = (B.abs().max(dim=1).values > 100).sum().item()
     assert big_a == 10 and big_b == 5
+
+
+def test_scaled_gemm_blockwise_form_brute_force():
+    # The per-tile form, written as explicit loops over K scale blocks with the scale
+    # indices (i // 128, kb) and (kb, j // 128), equals the dequantised product.
+    r = _rng(25)
+    M, N, K, t = 5, 7, 300, 128
+    A = r.standard_normal((M, K)) * 10.0 ** r.integers(-2, 3, (M, K))
+    B = r.standard_normal((K, N))
+    QA, SA = P.quantize_tiles_e4m3(A.astype(np.float32))
+    QB, SB = P.quantize_tiles_e4m3(B.astype(np.float32))
+    qa, qb = P.e4m3_decode(QA), P.e4m3_decode(QB)
+    brute = np.zeros((M, N))
+    for i in range(M):
+        for j in range(N):
+            tot = 0.0
+            for kb in range(-(-K // t)):
+                part = sum(qa[i, k] * qb[k, j] for k in range(kb * t, min(K, kb * t + t)))
+                tot += float(SA[i // t, kb]) * float(SB[kb, j // t]) * part
+            brute[i, j] = tot
+    got = P.gemm_scaled_expected(QA, SA, QB, SB, None, 1.0, 0.0, "fp8")
+    assert np.allclose(got, brute, rtol=1e-12, atol=1e-12)
