@@ -169,8 +169,17 @@ int tgemm_tile_map(int64_t M, int64_t N, int BM, int BN, int group_m, int xcd_re
 int tgemm_autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps,
                    const char* db_path);
 
-/* Load a tuning database (JSON lines) for the "tuned" policy. Host-only. */
+/* Load a tuning database (JSON lines) for the "tuned" policy: keeps the
+ * fastest valid record per (dtype, M, N, K, load width).  Lines that do not
+ * parse, records marked invalid and records of another schedule table (field
+ * "space" != tgemm_schedule_space_hash()) are skipped.  Returns the number of
+ * records used, or -TGEMM_INVALID_VALUE if the file cannot be opened.
+ * Host-only. */
 int tgemm_load_tuning_db(const char* db_path);
+
+/* Hash of the compiled schedule table (the "space" field of tuning records).
+ * Host-only. */
+uint64_t tgemm_schedule_space_hash(void);
 
 /* Schedule the current policy would pick for a problem.  Host-only. */
 int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,

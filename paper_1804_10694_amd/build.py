@@ -16,6 +16,7 @@ LIB = os.path.join(HERE, "libtgemm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "registry.cpp", "api.cpp", "select.cpp",
+           "tune.hip",
            "pending.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

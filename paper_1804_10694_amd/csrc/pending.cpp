@@ -11,7 +11,6 @@ int tgemm_batched(int64_t, const int64_t*, const int64_t*, const int64_t*, const
     return TGEMM_NOT_SUPPORTED;
 }
 
-int tgemm_autotune(int64_t, int64_t, int64_t, int, int, const char*) { return -TGEMM_NOT_SUPPORTED; }
 
 void tgemm_shutdown(void) {}
 

@@ -52,7 +52,57 @@ bool json_true(const char* line, const char* key)
     return std::strstr(line, pat) != nullptr;
 }
 
+bool json_hex(const char* line, const char* key, unsigned long long* out)
+{
+    char pat[64];
+    std::snprintf(pat, sizeof(pat), "\"%s\": \"", key);
+    const char* p = std::strstr(line, pat);
+    if (!p) return false;
+    p += std::strlen(pat);
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(p, &end, 16);
+    if (end == p) return false;
+    *out = v;
+    return true;
+}
+
+void register_locked(int dtype, int64_t M, int64_t N, int64_t K, int vec, const Choice& c, double ms)
+{
+    const auto key = std::make_tuple(dtype, M, N, K, vec);
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end() || ms < it->second.ms) g_tuned[key] = TunedEntry{c, ms};
+}
+
 }  // namespace
+
+void register_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, const Choice& c, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    register_locked(dtype, M, N, K, vec, c, ms);
+}
+
+namespace {
+// Fastest tuned record usable with the operands' alignment (16-byte loads
+// allowed -> both load widths compete).  Caller holds g_sel_mu.
+bool lookup_locked(int dtype, int64_t M, int64_t N, int64_t K, bool vec_allowed, Choice* out)
+{
+    const TunedEntry* best = nullptr;
+    for (int vec : {4, 1}) {
+        if (vec == 4 && !vec_allowed) continue;
+        auto it = g_tuned.find(std::make_tuple(dtype, M, N, K, vec));
+        if (it != g_tuned.end() && (!best || it->second.ms < best->ms)) best = &it->second;
+    }
+    if (!best) return false;
+    *out = best->choice;
+    return true;
+}
+}  // namespace
+
+bool lookup_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, Choice* out)
+{
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    return lookup_locked(dtype, M, N, K, vec > 1, out);
+}
 
 int find_schedule(int dtype, int BM, int BN, int BK, int vec)
 {
@@ -105,12 +155,7 @@ int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed
             return TGEMM_SUCCESS;
         }
     } else if (g_policy == POLICY_TUNED) {
-        const int vec = vec_allowed ? 4 : 1;
-        auto it = g_tuned.find(std::make_tuple(dtype, M, N, K, vec));
-        if (it != g_tuned.end()) {
-            *out = it->second.choice;
-            return TGEMM_SUCCESS;
-        }
+        if (lookup_locked(dtype, M, N, K, vec_allowed, out)) return TGEMM_SUCCESS;
     }
     return default_schedule(M, N, K, dtype, vec_allowed, out);
 }
@@ -151,6 +196,7 @@ extern "C" int tgemm_load_tuning_db(const char* db_path)
     if (!f) return -TGEMM_INVALID_VALUE;
     char line[4096];
     int used = 0;
+    const unsigned long long space = schedule_space_hash();
     std::lock_guard<std::mutex> lk(g_sel_mu);
     while (std::fgets(line, sizeof(line), f)) {
         if (!std::strchr(line, '\n') && !std::feof(f)) {  // overlong line: skip its rest
@@ -165,14 +211,13 @@ extern "C" int tgemm_load_tuning_db(const char* db_path)
             !json_number(line, "xcd", &xcd) || !json_number(line, "ms", &ms))
             continue;
         if (!json_true(line, "valid")) continue;
+        unsigned long long h = 0;
+        if (!json_hex(line, "space", &h) || h != space) continue;  // another schedule table
         const int sid = (int)id;
         if (sid < 0 || sid >= num_schedules() || schedule(sid).dtype != (int)dt) continue;
         if (gm < 1 || gm > 64 || !(ms > 0)) continue;
-        const auto key = std::make_tuple((int)dt, (int64_t)m, (int64_t)n, (int64_t)k, schedule(sid).vec);
-        auto it = g_tuned.find(key);
-        if (it == g_tuned.end() || ms < it->second.ms) {
-            g_tuned[key] = TunedEntry{Choice{sid, (int)gm, xcd != 0 ? 1 : 0}, ms};
-        }
+        register_locked((int)dt, (int64_t)m, (int64_t)n, (int64_t)k, schedule(sid).vec,
+                        Choice{sid, (int)gm, xcd != 0 ? 1 : 0}, ms);
         ++used;
     }
     std::fclose(f);
@@ -193,3 +238,5 @@ extern "C" int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,
     *xcd_remap = c.xcd_remap;
     return TGEMM_SUCCESS;
 }
+
+extern "C" uint64_t tgemm_schedule_space_hash(void) { return tg::schedule_space_hash(); }

@@ -22,4 +22,11 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
 // Index of the compiled schedule with these parameters, or -1.
 int find_schedule(int dtype, int BM, int BN, int BK, int vec);
 
+// Tuned choices (filled by the autotuner and by the database loader).
+void register_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, const Choice& c, double ms);
+bool lookup_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, Choice* out);
+
+// Hash of the compiled schedule table; tuning records of another table are ignored.
+uint64_t schedule_space_hash();
+
 }  // namespace tg

@@ -47,6 +47,8 @@ lib.tgemm_tile_map.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32, _pi32, _pi32,
 lib.tgemm_autotune.argtypes = [_i64, _i64, _i64, _i32, _i32, ctypes.c_char_p]
 lib.tgemm_load_tuning_db.argtypes = [ctypes.c_char_p]
 lib.tgemm_select_schedule.argtypes = [_i64, _i64, _i64, _i32, _pi32, _pi32, _pi32]
+lib.tgemm_schedule_space_hash.argtypes = []
+lib.tgemm_schedule_space_hash.restype = ctypes.c_uint64
 lib.tgemm_shutdown.argtypes = []
 lib.tgemm_shutdown.restype = None
 
@@ -239,6 +241,10 @@ def select_schedule(M, N, K, dtype):
     _check(lib.tgemm_select_schedule(M, N, K, _dtype_code(dtype), ctypes.byref(sid),
                                      ctypes.byref(gm), ctypes.byref(xcd)), "tgemm_select_schedule")
     return sid.value, gm.value, xcd.value
+
+
+def schedule_space_hash():
+    return int(lib.tgemm_schedule_space_hash())
 
 
 def shutdown():
