@@ -15,7 +15,16 @@ The cpu_baseline leg times the FP64 oracle on a bounded sample of rows of the
 8192^3 product (about ten seconds of host work) and reuses those rows to report
 the GPU paths' sampled normwise error.
 
+The extra_rows leg (outside the step and its value) measures the other rows of
+the path on their own workloads:
+  - per-128x128-tile scaled gemm at 16384^3 (A, B ~ N(0,1) with 1% of rows x1e3,
+    seed 30), quantised on the GPU, e4m3 and bf16, alpha = 1, beta = 0;
+  - the grouped persistent launch over 512 problems with M, N, K log-uniform in
+    [16, 2048] (seed 4, matrices from seeds 4000 + p), alpha = 1, beta = 0.5,
+    F32 and split-bf16x3, replayed from a HIP graph.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-extras]
 """
 import argparse
 import json
@@ -27,7 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "x3": 2516.6 / 3.0}   # MI355X dense: FP32 MFMA; bf16 MFMA / 3
+PEAK_TFLOPS = {"f32": 157.3, "x3": 2516.6 / 3.0,   # MI355X dense: FP32 MFMA; bf16 MFMA / 3
+               "bf16": 2516.6, "fp8": 5033.2}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -37,6 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target host time of the oracle sample")
     return ap.parse_args()
@@ -70,6 +81,80 @@ def cpu_baseline(A, B, C0, dev_results, seconds):
     for name, C in dev_results.items():
         errors[name] = oracle.normwise_error(C[rows], ref)
     return base, errors
+
+
+def _time_events(fn, reps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return sum(ts) / len(ts), ts[len(ts) // 2]
+
+
+def extra_rows(tg, inputs):
+    """Scaled low-precision gemm at 16384^3 and the 512-problem grouped launch."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    n = 16384
+    A, B = inputs.lowprec_inputs(n, n, n, seed=30)
+    Ad, Bd = A.to(dev), B.to(dev)
+    del A, B
+    C = torch.empty(n, n, device=dev)
+    flops = 2.0 * n ** 3
+    for dt in ("fp8", "bf16"):
+        qa, sa = tg.quantize_tiles(Ad, dt)
+        qb, sb = tg.quantize_tiles(Bd, dt)
+        q_avg, _ = _time_events(lambda: tg.quantize_tiles(Ad, dt), 5)
+        avg, med = _time_events(lambda: tg.gemm_scaled(qa, sa, qb, sb, C, 1.0, 0.0, dt), 10)
+        tf = flops / (avg * 1e-3) / 1e12
+        es = 1 if dt == "fp8" else 2
+        out[f"scaled_{dt}_16384"] = {
+            "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(tf, 1),
+            "peak_tflops": PEAK_TFLOPS[dt], "frac_peak": round(tf / PEAK_TFLOPS[dt], 4),
+            "schedule": tg.select_schedule(n, n, n, dt),
+            "quantize_ms_per_matrix": round(q_avg, 4),
+            "algorithmic_bytes": 2 * n * n * es + 4 * n * n}
+        del qa, qb
+    del Ad, Bd, C
+    torch.cuda.empty_cache()
+
+    dims = inputs.grouped_dims()
+    host = inputs.grouped_inputs(dims, 4000)
+    As = [h[0].to(dev) for h in host]
+    Bs = [h[1].to(dev) for h in host]
+    Cs = [h[2].to(dev) for h in host]
+    gflops = float(sum(2.0 * m * n_ * k for m, n_, k in dims))
+    gbytes = float(sum(4.0 * (m * k + k * n_ + 2 * m * n_) for m, n_, k in dims))
+    for dt in ("f32", "x3"):
+        al, be = [1.0] * len(dims), [0.5] * len(dims)
+        tg.gemm_batched(As, Bs, Cs, al, be, dt)          # plans
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            tg.gemm_batched(As, Bs, Cs, al, be, dt)
+        avg, med = _time_events(graph.replay, 20)
+        floor_ms = max(gflops / (PEAK_TFLOPS[dt] * 1e12), gbytes / (HBM_PEAK_GBS * 1e9)) * 1e3
+        out[f"grouped_{dt}_512"] = {
+            "avg_ms": round(avg, 4), "median_ms": round(med, 4),
+            "gemm_per_s": round(len(dims) / (avg * 1e-3), 1),
+            "tflops": round(gflops / (avg * 1e-3) / 1e12, 2),
+            "hbm_gbs_compulsory": round(gbytes / (avg * 1e-3) / 1e9, 1),
+            "floor_ms": round(floor_ms, 4), "frac_of_floor": round(floor_ms / avg, 4),
+            "bound": "mfma" if gflops / (PEAK_TFLOPS[dt] * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
+            else "hbm"}
+        del graph
+    return out
 
 
 def main():
@@ -155,6 +240,10 @@ def main():
     if not args.no_cpu_baseline:
         base, errors = cpu_baseline(*host[sq], results, args.cpu_seconds)
 
+    del devm, C
+    torch.cuda.empty_cache()
+    extras = None if args.no_extras else extra_rows(tg, inputs)
+
     x3 = per_path["x3_8192x8192x8192"]
     f32 = per_path["f32_8192x8192x8192"]
     out = {
@@ -172,6 +261,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": base,
         "sampled_normwise_error_8192": errors,
+        "extra_rows": extras,
     }
     print(json.dumps(out), flush=True)
 
