@@ -185,6 +185,36 @@ uint64_t tgemm_schedule_space_hash(void);
 int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,
                           int* schedule_id, int* group_m, int* xcd_remap);
 
+/*
+ * Cost-model network primitives (project addition; the Tiramisu paper,
+ * Sections I and II, notes that automatic schedulers lack a precise cost
+ * model).  A ReLU MLP with `layers` layers of widths dims[0..layers]
+ * (host array, dims[layers] == 1): Z_l = A_{l-1} W_l + b_l, A_l = relu(Z_l)
+ * except for the last layer.  `params` is one flat FP32 device vector, layer by
+ * layer: W_l (dims[l] x dims[l+1], row-major) then b_l.  X is rows x dims[0]
+ * row-major on the device; y and out have `rows` entries.  `work` is a device
+ * scratch buffer of tgemm_mlp_workspace_count() floats owned by the caller.
+ * Matrix products run on this library's F32 gemm (built-in schedule rule).
+ */
+int64_t tgemm_mlp_param_count(int layers, const int* dims);
+int64_t tgemm_mlp_workspace_count(int layers, const int* dims, int64_t rows);
+int tgemm_mlp_forward(int layers, const int* dims, const float* params, int64_t rows,
+                      const float* X, float* out, float* work, void* stream);
+/*
+ * One training step on a batch: forward, loss = mean((out - y)^2) written to
+ * the device scalar `loss`, gradients by the chain rule into `grads` (same
+ * layout as params; the derivative of relu at 0 is 0), then one Adam update
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with `step` >= 1) of
+ * params, adam_m and adam_v.  lr == 0 leaves params unchanged.
+ */
+int tgemm_mlp_train_step(int layers, const int* dims, float* params, float* grads,
+                         float* adam_m, float* adam_v, int64_t step, float lr, int64_t rows,
+                         const float* X, const float* y, float* loss, float* work, void* stream);
+
+/* The Adam update of tgemm_mlp_train_step alone, on n parameters. */
+int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m, float* adam_v,
+                    int64_t step, float lr, void* stream);
+
 /* Frees plan caches and workspaces owned by the library. */
 void tgemm_shutdown(void);
 

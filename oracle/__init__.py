@@ -12,6 +12,9 @@ Contents
                   the per-tile quantiser (project precision forms; their
                   readings are stated in each function).
   normwise_error  ||X - R||_F / ||R||_F in FP64.
+  mlp             FP64 ReLU MLP, MSE loss, chain-rule gradients and Adam
+                  (the cost model's network).
 """
 from .gemm import gemm, gemm_rows, num_threads, normwise_error, lib_path  # noqa: F401
 from . import precision  # noqa: F401
+from . import mlp  # noqa: F401

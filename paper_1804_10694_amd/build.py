@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtgemm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "batched.hip", "tune.hip", "registry.cpp",
-           "api.cpp", "select.cpp"]
+SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "batched.hip", "tune.hip", "mlp.hip",
+           "registry.cpp", "api.cpp", "select.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -47,6 +47,14 @@ lib.tgemm_tile_map.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32, _pi32, _pi32,
 lib.tgemm_autotune.argtypes = [_i64, _i64, _i64, _i32, _i32, ctypes.c_char_p]
 lib.tgemm_load_tuning_db.argtypes = [ctypes.c_char_p]
 lib.tgemm_select_schedule.argtypes = [_i64, _i64, _i64, _i32, _pi32, _pi32, _pi32]
+lib.tgemm_mlp_param_count.argtypes = [_i32, _pi32]
+lib.tgemm_mlp_param_count.restype = ctypes.c_int64
+lib.tgemm_mlp_workspace_count.argtypes = [_i32, _pi32, _i64]
+lib.tgemm_mlp_workspace_count.restype = ctypes.c_int64
+lib.tgemm_mlp_forward.argtypes = [_i32, _pi32, _p, _i64, _p, _p, _p, _p]
+lib.tgemm_mlp_train_step.argtypes = [_i32, _pi32, _p, _p, _p, _p, _i64, _f32, _i64, _p, _p, _p, _p,
+                                     _p]
+lib.tgemm_adam_step.argtypes = [_i64, _p, _p, _p, _p, _i64, _f32, _p]
 lib.tgemm_schedule_space_hash.argtypes = []
 lib.tgemm_schedule_space_hash.restype = ctypes.c_uint64
 lib.tgemm_shutdown.argtypes = []
@@ -245,6 +253,51 @@ def select_schedule(M, N, K, dtype):
 
 def schedule_space_hash():
     return int(lib.tgemm_schedule_space_hash())
+
+
+def _dims(dims):
+    return (ctypes.c_int32 * len(dims))(*dims), len(dims) - 1
+
+
+def mlp_param_count(dims):
+    d, layers = _dims(dims)
+    n = lib.tgemm_mlp_param_count(layers, d)
+    if n < 0:
+        raise TgemmError(-n, "tgemm_mlp_param_count")
+    return n
+
+
+def mlp_workspace(dims, rows, device="cuda"):
+    d, layers = _dims(dims)
+    n = lib.tgemm_mlp_workspace_count(layers, d, rows)
+    if n < 0:
+        raise TgemmError(-n, "tgemm_mlp_workspace_count")
+    return torch.empty(n, dtype=torch.float32, device=device)
+
+
+def mlp_forward(dims, params, X, out=None, work=None, stream=None):
+    d, layers = _dims(dims)
+    rows = X.shape[0]
+    if out is None:
+        out = torch.empty(rows, dtype=torch.float32, device=X.device)
+    if work is None:
+        work = mlp_workspace(dims, rows, X.device)
+    _check(lib.tgemm_mlp_forward(layers, d, params.data_ptr(), rows, X.data_ptr(), out.data_ptr(),
+                                 work.data_ptr(), _stream_handle(stream)), "tgemm_mlp_forward")
+    return out
+
+
+def mlp_train_step(dims, params, grads, m, v, step, lr, X, y, loss, work, stream=None):
+    d, layers = _dims(dims)
+    _check(lib.tgemm_mlp_train_step(layers, d, params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                                    v.data_ptr(), step, lr, X.shape[0], X.data_ptr(), y.data_ptr(),
+                                    loss.data_ptr(), work.data_ptr(), _stream_handle(stream)),
+           "tgemm_mlp_train_step")
+
+
+def adam_step(params, grads, m, v, step, lr, stream=None):
+    _check(lib.tgemm_adam_step(params.numel(), params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                               v.data_ptr(), step, lr, _stream_handle(stream)), "tgemm_adam_step")
 
 
 def shutdown():

@@ -288,3 +288,58 @@ def test_scaled_gemm_blockwise_form_brute_force():
             brute[i, j] = tot
     got = P.gemm_scaled_expected(QA, SA, QB, SB, None, 1.0, 0.0, "fp8")
     assert np.allclose(got, brute, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------- MLP (cost model)
+from oracle import mlp as O  # noqa: E402
+
+
+def _net(seed, dims):
+    r = _rng(seed)
+    return r.standard_normal(O.param_count(dims)) * 0.3
+
+
+def test_mlp_gradients_match_central_differences():
+    dims = [5, 7, 6, 1]
+    p = _net(30, dims)
+    r = _rng(31)
+    X, y = r.standard_normal((9, 5)), r.standard_normal(9)
+    _, g = O.gradients(p, dims, X, y)
+    h = 1e-6
+    num = np.empty_like(p)
+    for i in range(len(p)):
+        e = np.zeros_like(p)
+        e[i] = h
+        num[i] = (O.loss(p + e, dims, X, y) - O.loss(p - e, dims, X, y)) / (2 * h)
+    assert np.max(np.abs(num - g)) <= 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def test_mlp_zero_weights_output_is_last_bias():
+    dims = [4, 8, 8, 1]
+    p = np.zeros(O.param_count(dims))
+    p[-1] = 0.75
+    out, _ = O.forward(p, dims, _rng(32).standard_normal((6, 4)))
+    assert np.array_equal(out, np.full(6, 0.75))
+
+
+def test_mlp_linear_layer_closed_form():
+    # one linear layer: out = X w + b, dW = X^T dY with dY = 2 (out - y) / n
+    r = _rng(33)
+    dims = [3, 1]
+    X, y = r.standard_normal((11, 3)), r.standard_normal(11)
+    p = r.standard_normal(O.param_count(dims))
+    L, g = O.gradients(p, dims, X, y)
+    out = X @ p[:3] + p[3]
+    dY = 2.0 * (out - y) / 11
+    assert np.allclose(g[:3], X.T @ dY, rtol=1e-14, atol=1e-14)
+    assert np.isclose(g[3], dY.sum(), rtol=1e-14, atol=1e-14)
+    assert np.isclose(L, np.mean((out - y) ** 2), rtol=1e-14)
+
+
+def test_adam_first_step_closed_form():
+    # at step 1 the bias-corrected moments are g and g^2, so the update is
+    # lr * g / (|g| + eps): a step of about lr against the sign of g
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    p, m, v = O.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
+    assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
