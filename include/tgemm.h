@@ -138,7 +138,10 @@ const char* tgemm_status_string(int status);
 /*
  * Schedule-selection policy for tgemm (Section VI-A: tile size found by
  * measurement).  "default" (built-in rule), "tuned" (the tuning database,
- * else default), "force:<id>" (one schedule id for every call it serves).
+ * else default), "model" (the loaded cost model's argmin; shapes outside its
+ * training range, and new shapes while the stream is being captured, fall back
+ * to the tuning database, then to the rule), "force:<id>" (one schedule id for
+ * every call it serves).
  * Returns TGEMM_INVALID_VALUE for an unknown policy string.
  */
 int tgemm_set_policy(const char* policy);
@@ -181,7 +184,8 @@ int tgemm_load_tuning_db(const char* db_path);
  * Host-only. */
 uint64_t tgemm_schedule_space_hash(void);
 
-/* Schedule the current policy would pick for a problem.  Host-only. */
+/* Schedule the current policy would pick for a dense problem (row strides K
+ * and N, 16-byte aligned bases).  Host-only. */
 int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,
                           int* schedule_id, int* group_m, int* xcd_remap);
 
@@ -214,6 +218,49 @@ int tgemm_mlp_train_step(int layers, const int* dims, float* params, float* grad
 /* The Adam update of tgemm_mlp_train_step alone, on n parameters. */
 int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m, float* adam_v,
                     int64_t step, float lr, void* stream);
+
+/*
+ * Learned cost model (project addition).  A 20-feature ReLU MLP (3 hidden
+ * layers of 256) predicts the log runtime of (problem, schedule, tile order).
+ *
+ * tgemm_costmodel_train: reads the valid records of a tuning database written
+ *   by tgemm_autotune (records of another schedule table are skipped),
+ *   normalises features and targets, trains with minibatch Adam on the GPU
+ *   (tgemm_mlp_train_step; `epochs` passes, learning rate decaying linearly
+ *   from lr to lr/10, He-normal initialisation from `seed`), and writes the
+ *   weight file: network, normalisation, training range, Adam state and the
+ *   schedule-table hash.  *final_loss (may be NULL) receives the last batch's
+ *   normalised MSE.
+ * tgemm_costmodel_load: reads a weight file; TGEMM_NOT_SUPPORTED if it was
+ *   trained for another schedule table, TGEMM_INVALID_VALUE if it is not a
+ *   weight file of this version.  tgemm_costmodel_unload forgets the model.
+ * tgemm_costmodel_predict: argmin of the predicted runtime over every
+ *   candidate of a dense problem (row strides K and N, 16-byte aligned bases);
+ *   TGEMM_NOT_SUPPORTED without a model or when log2 M, N or K lies more than
+ *   0.5 outside the training range.
+ * tgemm_costmodel_predict_all: predictions for every candidate of a dtype
+ *   (host output arrays of max_rows entries); returns the row count or a
+ *   negative status.
+ * tgemm_costmodel_select: the prediction when the model can answer, else
+ *   exhaustive autotuning (tgemm_autotune with `reps`, appending to db_path);
+ *   *used_fallback says which.
+ * tgemm_costmodel_features: the feature vector (20 floats, host) of one
+ *   candidate.  Host-only.
+ */
+int tgemm_costmodel_train(const char* db_path, const char* weights_out, int epochs, int batch,
+                          float lr, uint64_t seed, float* final_loss);
+int tgemm_costmodel_load(const char* weights_path);
+void tgemm_costmodel_unload(void);
+int tgemm_costmodel_predict(int64_t M, int64_t N, int64_t K, int dtype, int* schedule_id,
+                            int* group_m, int* xcd_remap, float* predicted_ms);
+int tgemm_costmodel_predict_all(int64_t M, int64_t N, int64_t K, int dtype, int max_rows,
+                                int* schedule_id, int* group_m, int* xcd_remap,
+                                float* predicted_ms);
+int tgemm_costmodel_select(int64_t M, int64_t N, int64_t K, int dtype, int reps,
+                           const char* db_path, int* schedule_id, int* group_m, int* xcd_remap,
+                           int* used_fallback);
+int tgemm_costmodel_features(int64_t M, int64_t N, int64_t K, int dtype, int schedule_id,
+                             int group_m, int xcd_remap, float* out);
 
 /* Frees plan caches and workspaces owned by the library. */
 void tgemm_shutdown(void);

@@ -16,6 +16,7 @@ LIB = os.path.join(HERE, "libtgemm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "batched.hip", "tune.hip", "mlp.hip",
+           "costmodel.hip",
            "registry.cpp", "api.cpp", "select.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -130,6 +130,12 @@ int run_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int6
     return launch_gemm(d, a, s) == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
 }
 
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 int run_gemm(int id, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
              const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int group_m,
              int xcd_remap, hipStream_t stream)
@@ -172,7 +178,7 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t l
         return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
                                                                              : TGEMM_LAUNCH_FAILED;
     Choice ch;
-    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch);
+    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch, !stream_capturing(s));
     if (rc != TGEMM_SUCCESS) return rc;
     if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)  // unscaled: every scale is 1
         return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype,
@@ -218,7 +224,7 @@ int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, in
         return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
                                                                              : TGEMM_LAUNCH_FAILED;
     Choice ch;
-    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch);
+    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch, !stream_capturing(s));
     if (rc != TGEMM_SUCCESS) return rc;
     return run_scaled(M, N, K, alpha, A, lda, scaleA, B, ldb, scaleB, beta, C, ldc, dtype, ch.id,
                       ch.group_m, ch.xcd_remap, s);

@@ -16,7 +16,7 @@ namespace tg {
 
 namespace {
 
-enum Policy { POLICY_DEFAULT = 0, POLICY_TUNED = 1, POLICY_FORCE = 2 };
+enum Policy { POLICY_DEFAULT = 0, POLICY_TUNED = 1, POLICY_FORCE = 2, POLICY_MODEL = 3 };
 
 struct TunedEntry {
     Choice choice;
@@ -104,6 +104,12 @@ bool lookup_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, Choice* o
     return lookup_locked(dtype, M, N, K, vec > 1, out);
 }
 
+bool dense_vec_ok(int64_t N, int64_t K, int dtype)
+{
+    const int64_t es = dtype == TGEMM_BF16 ? 2 : (dtype == TGEMM_FP8_E4M3 ? 1 : 4);
+    return (K * es) % 16 == 0 && (N * es) % 16 == 0;
+}
+
 int find_schedule(int dtype, int BM, int BN, int BK, int vec)
 {
     for (int i = 0; i < num_schedules(); ++i) {
@@ -142,19 +148,33 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     return TGEMM_SUCCESS;
 }
 
-int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
+int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out,
+                    bool may_run_model)
 {
-    std::lock_guard<std::mutex> lk(g_sel_mu);
-    if (g_policy == POLICY_FORCE) {
-        const int id = g_force_id;
-        if (id >= 0 && id < num_schedules() && schedule(id).dtype == dtype &&
-            (schedule(id).vec == 1 || vec_allowed)) {
-            out->id = id;
-            out->group_m = 8;
-            out->xcd_remap = 1;
-            return TGEMM_SUCCESS;
+    Policy pol;
+    int force_id;
+    {
+        std::lock_guard<std::mutex> lk(g_sel_mu);
+        pol = g_policy;
+        force_id = g_force_id;
+        if (pol == POLICY_FORCE) {
+            if (force_id >= 0 && force_id < num_schedules() && schedule(force_id).dtype == dtype &&
+                (schedule(force_id).vec == 1 || vec_allowed)) {
+                out->id = force_id;
+                out->group_m = 8;
+                out->xcd_remap = 1;
+                return TGEMM_SUCCESS;
+            }
+        } else if (pol == POLICY_TUNED) {
+            if (lookup_locked(dtype, M, N, K, vec_allowed, out)) return TGEMM_SUCCESS;
         }
-    } else if (g_policy == POLICY_TUNED) {
+    }
+    if (pol == POLICY_MODEL) {
+        // a cached prediction costs nothing; a new one runs the network on the GPU,
+        // which is not allowed while the caller's stream is being captured
+        if (costmodel_cached(M, N, K, dtype, vec_allowed, out)) return TGEMM_SUCCESS;
+        if (may_run_model && costmodel_choose(M, N, K, dtype, vec_allowed, out)) return TGEMM_SUCCESS;
+        std::lock_guard<std::mutex> lk(g_sel_mu);
         if (lookup_locked(dtype, M, N, K, vec_allowed, out)) return TGEMM_SUCCESS;
     }
     return default_schedule(M, N, K, dtype, vec_allowed, out);
@@ -171,6 +191,8 @@ extern "C" int tgemm_set_policy(const char* policy)
         g_policy = POLICY_DEFAULT;
     } else if (std::strcmp(policy, "tuned") == 0) {
         g_policy = POLICY_TUNED;
+    } else if (std::strcmp(policy, "model") == 0) {
+        g_policy = POLICY_MODEL;
     } else if (std::strncmp(policy, "force:", 6) == 0) {
         char* end = nullptr;
         const long id = std::strtol(policy + 6, &end, 10);
@@ -231,7 +253,7 @@ extern "C" int tgemm_select_schedule(int64_t M, int64_t N, int64_t K, int dtype,
     if (!schedule_id || !group_m || !xcd_remap) return TGEMM_INVALID_VALUE;
     if (M < 0 || N < 0 || K < 0) return TGEMM_INVALID_VALUE;
     Choice c;
-    const int rc = select_schedule(M, N, K, dtype, true, &c);
+    const int rc = select_schedule(M, N, K, dtype, dense_vec_ok(N, K, dtype), &c, true);
     if (rc != TGEMM_SUCCESS) return rc;
     *schedule_id = c.id;
     *group_m = c.group_m;

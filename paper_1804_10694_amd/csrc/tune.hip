@@ -6,7 +6,8 @@
 // dtype is tried with every tile-order variant (group_m, XCD remap):
 //   1. correctness gate: small-integer inputs, where every partial sum is an
 //      exact integer, so the schedule's result must equal, bit for bit, the
-//      result of a plain one-thread-per-element integer kernel;
+//      result of a plain one-thread-per-element integer kernel (on a leading
+//      sub-problem with the same tile structure when the problem is large);
 //   2. warm-up, then `reps` launches timed one by one with HIP events; the
 //      median is recorded.
 // Each measurement is appended as one JSON line to the database file; keys
@@ -91,28 +92,32 @@ __global__ void fill_float_kernel(float* p, int64_t n, float v)
         p[i] = v;
 }
 
-// Plain integer reference: one thread per element of C, exact int64 sum.
-__global__ void int_gemm_kernel(int M, int N, int K, const int8_t* A, const int8_t* B, float* C)
+// Plain integer reference: one thread per element of C (gM x gN, compact), exact
+// int64 sum over A (row stride lda) and B (row stride ldb).
+__global__ void int_gemm_kernel(int gM, int gN, int gK, const int8_t* A, int64_t lda,
+                                const int8_t* B, int64_t ldb, float* C)
 {
-    const int64_t total = (int64_t)M * N;
+    const int64_t total = (int64_t)gM * gN;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx / N, j = idx % N;
+        const int64_t i = idx / gN, j = idx % gN;
         long long s = 0;
-        for (int k = 0; k < K; ++k) s += (long long)A[i * K + k] * B[(int64_t)k * N + j];
+        for (int k = 0; k < gK; ++k) s += (long long)A[i * lda + k] * B[(int64_t)k * ldb + j];
         C[idx] = (float)s;
     }
 }
 
-// Per-block count of elements whose bits differ.
-__global__ void __launch_bounds__(256) mismatch_kernel(const float* X, const float* Y, int64_t n,
-                                                       int* counts)
+// Per-block count of elements of X (gM x gN, row stride ldx) whose bits differ
+// from the compact reference Y.
+__global__ void __launch_bounds__(256) mismatch_kernel(const float* X, int64_t ldx, const float* Y,
+                                                       int gM, int gN, int* counts)
 {
     __shared__ int red[256];
     int c = 0;
+    const int64_t n = (int64_t)gM * gN;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        c += (__float_as_uint(X[i]) != __float_as_uint(Y[i])) ? 1 : 0;
+        c += (__float_as_uint(X[(i / gN) * ldx + i % gN]) != __float_as_uint(Y[i])) ? 1 : 0;
     red[threadIdx.x] = c;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -203,6 +208,11 @@ void read_done(const char* path, uint64_t hash, std::set<std::string>* done)
 
 }  // namespace
 
+// The correctness gate runs on a leading sub-problem whose sizes keep their
+// residues modulo 256 (every macro-tile and K panel size divides 256), so the
+// schedule meets the same full/partial tile structure at a bounded cost.
+static int64_t gate_dim(int64_t d) { return d <= 1024 ? d : 768 + d % 256; }
+
 // Tile-order variants tried for every compiled schedule.
 static const int kOrderVariants[][2] = {{1, 0}, {4, 1}, {8, 1}, {16, 1}};
 
@@ -223,8 +233,9 @@ int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* d
     DevBuf A, B, C, R, Ai, Bi, SA, SB, cnt;
     const int64_t nA = M * K, nB = K * N, nC = M * N;
     const int64_t nsa = ((M + 127) / 128) * ((K + 127) / 128), nsb = ((K + 127) / 128) * ((N + 127) / 128);
-    const unsigned cgrid = grid_for(nC);
-    if (!A.alloc(nA * es) || !B.alloc(nB * es) || !C.alloc(nC * 4) || !R.alloc(nC * 4) ||
+    const int64_t gM = gate_dim(M), gN = gate_dim(N), gK = gate_dim(K);
+    const unsigned cgrid = grid_for(gM * gN);
+    if (!A.alloc(nA * es) || !B.alloc(nB * es) || !C.alloc(nC * 4) || !R.alloc(gM * gN * 4) ||
         !Ai.alloc(nA) || !Bi.alloc(nB) || !SA.alloc(nsa * 4) || !SB.alloc(nsb * 4) ||
         !cnt.alloc(cgrid * sizeof(int)))
         return -TGEMM_ALLOC_FAILED;
@@ -241,18 +252,20 @@ int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* d
                        0x9876u, dtype);
     hipLaunchKernelGGL(fill_float_kernel, dim3(grid_for(nsa)), dim3(256), 0, s, (float*)SA.p, nsa, 1.f);
     hipLaunchKernelGGL(fill_float_kernel, dim3(grid_for(nsb)), dim3(256), 0, s, (float*)SB.p, nsb, 1.f);
-    hipLaunchKernelGGL(int_gemm_kernel, dim3(grid_for(nC)), dim3(256), 0, s, (int)M, (int)N, (int)K,
-                       (const int8_t*)Ai.p, (const int8_t*)Bi.p, (float*)R.p);
+    hipLaunchKernelGGL(int_gemm_kernel, dim3(grid_for(gM * gN)), dim3(256), 0, s, (int)gM, (int)gN,
+                       (int)gK, (const int8_t*)Ai.p, K, (const int8_t*)Bi.p, N, (float*)R.p);
     if (hipStreamSynchronize(s) != hipSuccess) {
         (void)hipStreamDestroy(s);
         return -TGEMM_LAUNCH_FAILED;
     }
 
-    auto launch = [&](int sid, int gm, int xcd, float* out) {
+    // (m, n, k) = the full problem for timing, the gate sub-problem for checking;
+    // the row strides stay those of the full buffers.
+    auto launch = [&](int sid, int gm, int xcd, float* out, int64_t m, int64_t n, int64_t k) {
         if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)
-            return run_scaled(M, N, K, 1.f, A.p, K, (const float*)SA.p, B.p, N, (const float*)SB.p,
+            return run_scaled(m, n, k, 1.f, A.p, K, (const float*)SA.p, B.p, N, (const float*)SB.p,
                               0.f, out, N, dtype, sid, gm, xcd, s);
-        return run_gemm(sid, M, N, K, 1.f, A.p, K, B.p, N, 0.f, out, N, gm, xcd, s);
+        return run_gemm(sid, m, n, k, 1.f, A.p, K, B.p, N, 0.f, out, N, gm, xcd, s);
     };
 
     // A run killed mid-line leaves a torn last line: start on a fresh line.
@@ -282,12 +295,12 @@ int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* d
             const int gm = ov[0], xcd = ov[1];
             if (done.count(key_of(dtype, M, N, K, sid, gm, xcd, hash))) continue;
             // 1. correctness gate
-            hipLaunchKernelGGL(fill_float_kernel, dim3(cgrid), dim3(256), 0, s, (float*)C.p, nC,
+            hipLaunchKernelGGL(fill_float_kernel, dim3(grid_for(nC)), dim3(256), 0, s, (float*)C.p, nC,
                                __builtin_nanf(""));
-            bool valid = launch(sid, gm, xcd, (float*)C.p) == TGEMM_SUCCESS;
+            bool valid = launch(sid, gm, xcd, (float*)C.p, gM, gN, gK) == TGEMM_SUCCESS;
             if (valid) {
-                hipLaunchKernelGGL(mismatch_kernel, dim3(cgrid), dim3(256), 0, s, (const float*)C.p,
-                                   (const float*)R.p, nC, (int*)cnt.p);
+                hipLaunchKernelGGL(mismatch_kernel, dim3(cgrid), dim3(256), 0, s, (const float*)C.p, N,
+                                   (const float*)R.p, (int)gM, (int)gN, (int*)cnt.p);
                 valid = hipMemcpyAsync(hcnt.data(), cnt.p, cgrid * sizeof(int), hipMemcpyDeviceToHost,
                                        s) == hipSuccess &&
                         hipStreamSynchronize(s) == hipSuccess;
@@ -298,10 +311,10 @@ int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* d
             // 2. timing
             double med = -1.0;
             if (valid) {
-                for (int w = 0; w < 2; ++w) launch(sid, gm, xcd, (float*)C.p);
+                for (int w = 0; w < 2; ++w) launch(sid, gm, xcd, (float*)C.p, M, N, K);
                 for (int r = 0; r < reps; ++r) {
                     (void)hipEventRecord(e0, s);
-                    launch(sid, gm, xcd, (float*)C.p);
+                    launch(sid, gm, xcd, (float*)C.p, M, N, K);
                     (void)hipEventRecord(e1, s);
                     (void)hipEventSynchronize(e1);
                     float ms = 0.f;

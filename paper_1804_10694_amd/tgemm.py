@@ -55,6 +55,17 @@ lib.tgemm_mlp_forward.argtypes = [_i32, _pi32, _p, _i64, _p, _p, _p, _p]
 lib.tgemm_mlp_train_step.argtypes = [_i32, _pi32, _p, _p, _p, _p, _i64, _f32, _i64, _p, _p, _p, _p,
                                      _p]
 lib.tgemm_adam_step.argtypes = [_i64, _p, _p, _p, _p, _i64, _f32, _p]
+lib.tgemm_costmodel_train.argtypes = [ctypes.c_char_p, ctypes.c_char_p, _i32, _i32, _f32,
+                                      ctypes.c_uint64, _pf32]
+lib.tgemm_costmodel_load.argtypes = [ctypes.c_char_p]
+lib.tgemm_costmodel_unload.argtypes = []
+lib.tgemm_costmodel_unload.restype = None
+lib.tgemm_costmodel_predict.argtypes = [_i64, _i64, _i64, _i32, _pi32, _pi32, _pi32, _pf32]
+lib.tgemm_costmodel_predict_all.argtypes = [_i64, _i64, _i64, _i32, _i32, _pi32, _pi32, _pi32,
+                                            _pf32]
+lib.tgemm_costmodel_select.argtypes = [_i64, _i64, _i64, _i32, _i32, ctypes.c_char_p, _pi32, _pi32,
+                                       _pi32, _pi32]
+lib.tgemm_costmodel_features.argtypes = [_i64, _i64, _i64, _i32, _i32, _i32, _i32, _pf32]
 lib.tgemm_schedule_space_hash.argtypes = []
 lib.tgemm_schedule_space_hash.restype = ctypes.c_uint64
 lib.tgemm_shutdown.argtypes = []
@@ -298,6 +309,58 @@ def mlp_train_step(dims, params, grads, m, v, step, lr, X, y, loss, work, stream
 def adam_step(params, grads, m, v, step, lr, stream=None):
     _check(lib.tgemm_adam_step(params.numel(), params.data_ptr(), grads.data_ptr(), m.data_ptr(),
                                v.data_ptr(), step, lr, _stream_handle(stream)), "tgemm_adam_step")
+
+
+def costmodel_train(db_path, weights_out, epochs=60, batch=512, lr=1e-3, seed=5):
+    loss = ctypes.c_float()
+    _check(lib.tgemm_costmodel_train(db_path.encode(), weights_out.encode(), epochs, batch, lr, seed,
+                                     ctypes.byref(loss)), "tgemm_costmodel_train")
+    return loss.value
+
+
+def costmodel_load(path):
+    _check(lib.tgemm_costmodel_load(path.encode()), "tgemm_costmodel_load")
+
+
+def costmodel_unload():
+    lib.tgemm_costmodel_unload()
+
+
+def costmodel_predict(M, N, K, dtype):
+    """(schedule, group_m, xcd, predicted_ms) or None when the model cannot answer."""
+    sid, gm, xcd, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    rc = lib.tgemm_costmodel_predict(M, N, K, _dtype_code(dtype), ctypes.byref(sid), ctypes.byref(gm),
+                                     ctypes.byref(xcd), ctypes.byref(ms))
+    if rc == NOT_SUPPORTED:
+        return None
+    _check(rc, "tgemm_costmodel_predict")
+    return sid.value, gm.value, xcd.value, ms.value
+
+
+def costmodel_predict_all(M, N, K, dtype, max_rows=4096):
+    sid = (ctypes.c_int32 * max_rows)()
+    gm = (ctypes.c_int32 * max_rows)()
+    xcd = (ctypes.c_int32 * max_rows)()
+    ms = (ctypes.c_float * max_rows)()
+    n = lib.tgemm_costmodel_predict_all(M, N, K, _dtype_code(dtype), max_rows, sid, gm, xcd, ms)
+    if n < 0:
+        raise TgemmError(-n, "tgemm_costmodel_predict_all")
+    return [(sid[i], gm[i], xcd[i], ms[i]) for i in range(n)]
+
+
+def costmodel_select(M, N, K, dtype, reps, db_path):
+    sid, gm, xcd, fb = (ctypes.c_int32() for _ in range(4))
+    _check(lib.tgemm_costmodel_select(M, N, K, _dtype_code(dtype), reps, db_path.encode(),
+                                      ctypes.byref(sid), ctypes.byref(gm), ctypes.byref(xcd),
+                                      ctypes.byref(fb)), "tgemm_costmodel_select")
+    return sid.value, gm.value, xcd.value, bool(fb.value)
+
+
+def costmodel_features(M, N, K, dtype, sid, group_m, xcd):
+    out = (ctypes.c_float * 20)()
+    _check(lib.tgemm_costmodel_features(M, N, K, _dtype_code(dtype), sid, group_m, xcd, out),
+           "tgemm_costmodel_features")
+    return list(out)
 
 
 def shutdown():
