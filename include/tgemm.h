@@ -95,7 +95,9 @@ int tgemm_with_schedule(int64_t M, int64_t N, int64_t K, float alpha,
  * ceil(K/128) x ceil(N/128), row stride ceil(N/128)); the last tiles may be
  * partial.  dtype: TGEMM_BF16 (A, B are uint16 bf16 patterns) or
  * TGEMM_FP8_E4M3 (A, B are bytes).  scaleA and scaleB are device pointers and
- * must not be NULL when A and B are read.
+ * must not be NULL when A and B are read.  Scales must be positive normal
+ * floats (packed schedules keep the running sum divided by the current scale
+ * product).
  */
 int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha,
                  const void* A, int64_t lda, const float* scaleA,
@@ -148,6 +150,10 @@ int tgemm_set_policy(const char* policy);
 
 /* Number of compiled schedules and the parameters of one of them.
  * info receives 8 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes.
+ * vec = 4: 16-byte global loads (16-byte aligned bases, row strides multiple of
+ * 16 bytes); vec = 1: 4-byte loads (any alignment); vec = 0: packed operands
+ * (a pre-pass copies A and B^T, converted and zero-padded, into a workspace
+ * the library owns per device and stream; any alignment).
  * Host-only: no HIP call. */
 int tgemm_schedule_count(void);
 int tgemm_schedule_info(int schedule_id, int* info);

@@ -119,6 +119,10 @@ int run_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int6
                const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                int64_t ldc, int dtype, int id, int group_m, int xcd_remap, hipStream_t s)
 {
+    const int pid = packed_index(id);
+    if (pid >= 0)
+        return run_packed(pid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, group_m,
+                          xcd_remap, s);
     const SchedDesc& d = schedule(id);
     GemmArgs a = make_args(d, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap);
     a.sA = sA;
@@ -140,6 +144,10 @@ int run_gemm(int id, int64_t M, int64_t N, int64_t K, float alpha, const void* A
              const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int group_m,
              int xcd_remap, hipStream_t stream)
 {
+    const int pid = packed_index(id);
+    if (pid >= 0)
+        return run_packed(pid, M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc,
+                          group_m, xcd_remap, stream);
     const SchedDesc& d = schedule(id);
     GemmArgs a = make_args(d, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap);
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
@@ -178,12 +186,23 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t l
         return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
                                                                              : TGEMM_LAUNCH_FAILED;
     Choice ch;
-    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch, !stream_capturing(s));
+    const bool capturing = stream_capturing(s);
+    const bool vok = vec_ok(A, lda, B, ldb, dtype);
+    rc = select_schedule(M, N, K, dtype, vok, &ch, !capturing);
     if (rc != TGEMM_SUCCESS) return rc;
-    if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)  // unscaled: every scale is 1
-        return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype,
-                          ch.id, ch.group_m, ch.xcd_remap, s);
-    return run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m, ch.xcd_remap, s);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3)  // unscaled: every scale is 1
+            rc = run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype,
+                            ch.id, ch.group_m, ch.xcd_remap, s);
+        else
+            rc = run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m,
+                          ch.xcd_remap, s);
+        // a packed schedule whose workspace would have to grow under capture: use the
+        // rule's schedule without packing instead
+        if (rc != TGEMM_CAPTURE_UNPLANNED) return rc;
+        if ((rc = direct_schedule(M, N, K, dtype, vok, &ch)) != TGEMM_SUCCESS) return rc;
+    }
+    return rc;
 }
 
 int tgemm_with_schedule(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
@@ -224,8 +243,14 @@ int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, in
         return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
                                                                              : TGEMM_LAUNCH_FAILED;
     Choice ch;
-    rc = select_schedule(M, N, K, dtype, vec_ok(A, lda, B, ldb, dtype), &ch, !stream_capturing(s));
+    const bool capturing = stream_capturing(s);
+    const bool vok = vec_ok(A, lda, B, ldb, dtype);
+    rc = select_schedule(M, N, K, dtype, vok, &ch, !capturing);
     if (rc != TGEMM_SUCCESS) return rc;
+    rc = run_scaled(M, N, K, alpha, A, lda, scaleA, B, ldb, scaleB, beta, C, ldc, dtype, ch.id,
+                    ch.group_m, ch.xcd_remap, s);
+    if (rc != TGEMM_CAPTURE_UNPLANNED) return rc;
+    if ((rc = direct_schedule(M, N, K, dtype, vok, &ch)) != TGEMM_SUCCESS) return rc;
     return run_scaled(M, N, K, alpha, A, lda, scaleA, B, ldb, scaleB, beta, C, ldc, dtype, ch.id,
                       ch.group_m, ch.xcd_remap, s);
 }

@@ -331,4 +331,5 @@ extern "C" void tgemm_shutdown(void)
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto& kv : g_plans) free_plan(kv.second);
     g_plans.clear();
+    packed_shutdown();
 }

@@ -10,7 +10,8 @@ struct SchedDesc {
     int dtype;      // tgemm_dtype this schedule serves
     int BM, BN, BK; // macro-tile (level-1 tiling) and K panel
     int WGM, WGN;   // wave grid: the macro-tile is split into WGM x WGN wave tiles
-    int vec;        // global load width in float32 elements (4 or 1)
+    int vec;        // global load width in float32 elements (4 or 1); 0 = packed operands
+                    // (any alignment: a pre-pass packs A and B into a workspace)
     int lds_bytes;  // LDS footprint (both stages)
     int threads;
     void (*kernel)(GemmArgs);
@@ -24,6 +25,17 @@ const SchedDesc& schedule(int id);
 // Per-translation-unit tables.
 const SchedDesc* tile_schedules(int* n);    // F32 and split-bf16x3
 const SchedDesc* scaled_schedules(int* n);  // bf16 and fp8 with per-tile scales
+const SchedDesc* packed_schedules(int* n);  // packed-operand x3, bf16, fp8
+
+// Packed schedules (gemm_packed.hip): index within packed_schedules().
+int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+               const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
+               int64_t ldc, int group_m, int xcd_remap, hipStream_t s);
+size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype);
+void packed_shutdown();
+void packed_release(hipStream_t s);  // frees the workspace of one stream
+// Position of a schedule id inside packed_schedules(), or -1.
+int packed_index(int id);
 
 // Stream-ordered launches (defined in the HIP translation units).
 hipError_t launch_gemm(const SchedDesc& d, const GemmArgs& a, hipStream_t s);

@@ -87,7 +87,7 @@ namespace {
 bool lookup_locked(int dtype, int64_t M, int64_t N, int64_t K, bool vec_allowed, Choice* out)
 {
     const TunedEntry* best = nullptr;
-    for (int vec : {4, 1}) {
+    for (int vec : {4, 1, 0}) {  // 0: packed operands, any alignment
         if (vec == 4 && !vec_allowed) continue;
         auto it = g_tuned.find(std::make_tuple(dtype, M, N, K, vec));
         if (it != g_tuned.end() && (!best || it->second.ms < best->ms)) best = &it->second;
@@ -110,23 +110,25 @@ bool dense_vec_ok(int64_t N, int64_t K, int dtype)
     return (K * es) % 16 == 0 && (N * es) % 16 == 0;
 }
 
-int find_schedule(int dtype, int BM, int BN, int BK, int vec)
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN)
 {
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
-        if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec) return i;
+        if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec &&
+            d.WGM == WGM && d.WGN == WGN)
+            return i;
     }
     return -1;
 }
 
-int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
+int direct_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
 {
     (void)K;
     const int vec = vec_allowed ? 4 : 1;
     auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
     int id = -1;
-    // Measured on MI355X at 8192^3: 128x128 macro-tiles beat 256-wide ones for both
-    // forms; 64-wide tiles keep small problems spread over the 256 CUs.
+    // Measured on MI355X at 8192^3: 128x128 macro-tiles beat 256-wide ones for the
+    // direct kernels; 64-wide tiles keep small problems spread over the 256 CUs.
     if (dtype == TGEMM_F32) {
         if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 32, vec);
         else id = find_schedule(dtype, 64, 64, 16, vec);
@@ -148,6 +150,26 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     return TGEMM_SUCCESS;
 }
 
+int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out)
+{
+    // Large 16/8-bit problems: packed operands with 256 x 256 macro-tiles and 8
+    // waves (the packing pass costs O(MK + KN) against O(MNK) of MFMA work).
+    auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+    if (dtype != TGEMM_F32 && K >= 512) {
+        const int bk = dtype == TGEMM_F32_BF16X3 ? 32 : (dtype == TGEMM_BF16 ? 64 : 128);
+        int id = -1;
+        if (tiles(256, 256) >= 256) id = find_schedule(dtype, 256, 256, bk, 0, 2, 4);
+        else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, bk, 0, 2, 2);
+        if (id >= 0) {
+            out->id = id;
+            out->group_m = 8;
+            out->xcd_remap = 1;
+            return TGEMM_SUCCESS;
+        }
+    }
+    return direct_schedule(M, N, K, dtype, vec_allowed, out);
+}
+
 int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out,
                     bool may_run_model)
 {
@@ -159,7 +181,7 @@ int select_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed
         force_id = g_force_id;
         if (pol == POLICY_FORCE) {
             if (force_id >= 0 && force_id < num_schedules() && schedule(force_id).dtype == dtype &&
-                (schedule(force_id).vec == 1 || vec_allowed)) {
+                (schedule(force_id).vec <= 1 || vec_allowed)) {
                 out->id = force_id;
                 out->group_m = 8;
                 out->xcd_remap = 1;

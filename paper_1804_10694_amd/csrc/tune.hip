@@ -344,6 +344,8 @@ int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* d
     std::fclose(db);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    packed_release(s);
     (void)hipStreamDestroy(s);
     if (best >= 0) register_tuned(dtype, M, N, K, schedule(best).vec, best_choice, best_ms);
     // entries measured by an earlier, interrupted run count too

@@ -136,6 +136,33 @@ def test_power_of_two_scales_exact(tg, dtype):
     np.testing.assert_array_equal(got.astype(np.float64), ref)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_packed_schedules_scaled_exact(tg, dtype):
+    # Every packed schedule (operands copied, B transposed, zero-padded) through the scaled
+    # entry point: integer codes with power-of-two scales that change across K blocks, so
+    # the running-sum rescaling at every 128-wide K block is exercised and must be exact.
+    M, N, K = 300, 270, 520
+    A, B, _ = inputs.integer_inputs(M, N, K, seed=37, r=8)
+    g = np.random.default_rng(38)
+    SA = (2.0 ** g.integers(-2, 3, P.scale_grid_shape(M, K))).astype(np.float32)
+    SB = (2.0 ** g.integers(-2, 3, P.scale_grid_shape(K, N))).astype(np.float32)
+    if dtype == "fp8":
+        QA, QB = P.e4m3_encode(A.numpy().astype(np.float64)), P.e4m3_encode(B.numpy().astype(np.float64))
+    else:
+        QA, QB = P.bf16_bits(A.numpy()), P.bf16_bits(B.numpy())
+    C0 = np.random.default_rng(39).integers(-4, 5, (M, N)).astype(np.float32)
+    ref = P.gemm_scaled_expected(QA, SA, QB, SB, C0, 1.0, 0.5, dtype)
+    packed = [sid for sid, info in tg.schedules(dtype) if info["vec"] == 0]
+    assert packed
+    try:
+        for sid in packed:
+            tg.set_policy(f"force:{sid}")
+            got = _gemm_scaled(tg, QA, SA, QB, SB, C0, 1.0, 0.5, dtype)
+            np.testing.assert_array_equal(got.astype(np.float64), ref, err_msg=f"schedule {sid}")
+    finally:
+        tg.set_policy("default")
+
+
 # ------------------------------------------------------------------ tolerance
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 @pytest.mark.parametrize("shape", [(512, 512, 1024), (300, 389, 517)])
