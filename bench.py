@@ -36,6 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+KERNEL_SOURCES = ["paper_1804_10694_amd/csrc/tile_f32x3.h", "paper_1804_10694_amd/csrc/gemm_tile.hip",
+                  "paper_1804_10694_amd/csrc/gemm_packed.hip", "paper_1804_10694_amd/csrc/kargs.h"]
+TRAFFIC_FILE = "profiles/traffic.json"
+
 PEAK_TFLOPS = {"f32": 157.3, "x3": 2516.6 / 3.0,   # MI355X dense: FP32 MFMA; bf16 MFMA / 3
                "bf16": 2516.6, "fp8": 5033.2}
 HBM_PEAK_GBS = 8000.0
@@ -48,9 +52,34 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one plain 1 GiB device copy (reference for the HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target host time of the oracle sample")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_symbol):
+    """HBM bytes per launch of `kernel_symbol` from the committed counter summary, or None
+    when there is none or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    rec = table.get(kernel_symbol)
+    if not rec or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(A, B, C0, dev_results, seconds):
@@ -221,9 +250,15 @@ def main():
     # dominant kernel = the path with the largest share of the step
     dom_key = max(per_path, key=lambda k: per_path[k]["avg_ms"])
     dom = per_path[dom_key]
-    roofline = {"bound": "mfma", "kernel": dom_key, "achieved": dom["tflops"],
+    dt_dom, shape_dom = [p for p in paths if f"{p[0]}_{p[1][0]}x{p[1][1]}x{p[1][2]}" == dom_key][0]
+    sym = tg.schedule_key(tg.select_schedule(*shape_dom, dt_dom)[0])
+    roofline = {"bound": "mfma", "kernel": dom_key, "kernel_symbol": sym, "achieved": dom["tflops"],
                 "peak": dom["peak_tflops"], "unit": "TFLOP/s",
-                "frac": round(dom["tflops"] / dom["peak_tflops"], 4), "traffic": None}
+                "frac": round(dom["tflops"] / dom["peak_tflops"], 4),
+                "traffic": measured_traffic(sym), "traffic_unit": "bytes per launch",
+                "compulsory_bytes": 4 * (shape_dom[0] * shape_dom[2] + shape_dom[2] * shape_dom[1]
+                                         + 2 * shape_dom[0] * shape_dom[1]),
+                "kernel_source_sha256": kernel_source_hash()}
 
     # fresh results for the error report (outside the timed region)
     results = {}
@@ -263,6 +298,12 @@ def main():
         "sampled_normwise_error_8192": errors,
         "extra_rows": extras,
     }
+    if args.copy_calibration:
+        # one plain device copy of 1 GiB: reads 2^30 bytes and writes 2^30 bytes of HBM
+        src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

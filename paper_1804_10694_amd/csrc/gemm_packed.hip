@@ -134,9 +134,10 @@ __global__ void __launch_bounds__(256) pack_cols_kernel(const void* X, int64_t l
 }
 
 // ------------------------------------------------------------------ main kernel
-template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_>
+template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_>
 struct PCfg {
     static constexpr int MODE = MODE_, BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
+    static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
     static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
     static constexpr int ES = (MODE == MODE_FP8) ? 1 : 2;
     static constexpr int KU = 16 / ES;                   // k per 16-byte unit
@@ -148,9 +149,11 @@ struct PCfg {
     static constexpr int NARR = (MODE == MODE_X3) ? 2 : 1;
     static constexpr int LDS_A = BM * UK * 16, LDS_B = BN * UK * 16;
     static constexpr int LDS_STAGE = NARR * (LDS_A + LDS_B);
-    static constexpr int LDS_BYTES = 2 * LDS_STAGE;
+    static constexpr int LDS_BYTES = NS * LDS_STAGE;
     // direct-to-LDS instructions (64 units each) per wave per array per panel
     static constexpr int A_INSTR = BM * UK / 64 / NW, B_INSTR = BN * UK / 64 / NW;
+    static constexpr int LOADS_PER_STAGE = NARR * (A_INSTR + B_INSTR);
+    static_assert(NS >= 2 && (NS - 2) * LOADS_PER_STAGE <= 63, "vmcnt holds at most 63");
     static_assert(BK % MK == 0 && kPackK % BK == 0 && 128 % BK == 0, "panels tile K");
     static_assert(BM <= kPackRows && BN <= kPackRows && kPackRows % BM == 0 && kPackRows % BN == 0,
                   "tiles divide the packed row padding");
@@ -198,6 +201,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const char* base, in
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, bytes, 0x00020000);
 }
 
+// s_waitcnt vmcnt(N) with expcnt and lgkmcnt left unconstrained (gfx9 encoding:
+// vmcnt[3:0] in bits 3:0, vmcnt[5:4] in bits 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
 struct PackedArgs {
     const char* A;    // packed A (hi), Rp_a x Kp
     const char* Alo;  // x3: packed A lo
@@ -212,85 +223,118 @@ struct PackedArgs {
     int tiles_m, tiles_n, group_m, xcd_remap;
 };
 
+// Operands of one MFMA group (MK consecutive k) for all of a wave's blocks.
+template <class CF>
+struct PkOps {
+    static constexpr int AV = (CF::MODE == MODE_FP8) ? 2 : 1;  // 16-byte units per operand
+    static constexpr int NA = (CF::MODE == MODE_X3) ? 2 : 1;   // hi (+ lo)
+    u32x4 a[NA][CF::TM][AV];
+    u32x4 b[NA][CF::TN][AV];
+};
+
+template <class CF>
+__device__ __forceinline__ void pk_load(const char* stage, PkOps<CF>& o, int g, int wm0, int wn0,
+                                        int lane)
+{
+    constexpr int UK = CF::UK, UPL = CF::UPL;
+    const int h = lane >> 5, l32 = lane & 31;
+#pragma unroll
+    for (int v = 0; v < PkOps<CF>::AV; ++v) {
+        const int u = (2 * g + h) * UPL + v;
+#pragma unroll
+        for (int x = 0; x < PkOps<CF>::NA; ++x) {
+            const char* la = stage + x * CF::LDS_A;
+            const char* lb = stage + CF::NARR * CF::LDS_A + x * CF::LDS_B;
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+                o.a[x][i][v] = *reinterpret_cast<const u32x4*>(la + pk_slot<UK>(wm0 + 32 * i + l32, u) * 16);
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j)
+                o.b[x][j][v] = *reinterpret_cast<const u32x4*>(lb + pk_slot<UK>(wn0 + 32 * j + l32, u) * 16);
+        }
+    }
+}
+
+template <class CF>
+__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN])
+{
+    if (CF::MODE == MODE_FP8) {
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const u32x4 a0 = o.a[0][i][0], a1 = o.a[0][i][PkOps<CF>::AV - 1];
+                const u32x4 b0 = o.b[0][j][0], b1 = o.b[0][j][PkOps<CF>::AV - 1];
+                const i32x8 x = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                                 (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                const i32x8 y = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                                 (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+                // format codes 0/0: both operands OCP e4m3; no block scaling
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[i][j], 0, 0, 0, 0, 0, 0);
+            }
+    } else {
+        if (CF::MODE == MODE_X3) {
+            // small terms first: lo*hi, hi*lo, then hi*hi
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, o.a[PkOps<CF>::NA - 1][i][0]),
+                        __builtin_bit_cast(bf16x8, o.b[0][j][0]), acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, o.a[0][i][0]),
+                        __builtin_bit_cast(bf16x8, o.b[PkOps<CF>::NA - 1][j][0]), acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, o.a[0][i][0]), __builtin_bit_cast(bf16x8, o.b[0][j][0]),
+                    acc[i][j], 0, 0, 0);
+    }
+}
+
+// MFMAs over one LDS stage.  Operand registers are double-buffered: the reads
+// of group g + 1 are issued before the MFMAs of group g, and the scheduler is
+// asked to interleave them, so LDS latency hides behind the matrix unit.
 template <class CF>
 __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
                                        int wn0, int lane)
 {
-    constexpr int UK = CF::UK, UPL = CF::UPL;
-    const char* a_hi = stage;
-    const char* a_lo = stage + CF::LDS_A;
-    const char* b_hi = stage + CF::NARR * CF::LDS_A;
-    const char* b_lo = b_hi + CF::LDS_B;
-    const int h = lane >> 5, l32 = lane & 31;
+    constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
+    constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : 1);
+    PkOps<CF> ops[2];
+    pk_load<CF>(stage, ops[0], 0, wm0, wn0, lane);
 #pragma unroll
     for (int g = 0; g < CF::NG; ++g) {
-        if (CF::MODE == MODE_FP8) {
-            i32x8 av[CF::TM], bv[CF::TN];
+        if (g + 1 < CF::NG) pk_load<CF>(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
+        pk_compute<CF>(ops[g & 1], acc);
+        if (g + 1 < CF::NG) {
+            // one LDS read between consecutive MFMAs while both last
 #pragma unroll
-            for (int i = 0; i < CF::TM; ++i) {
-                const int row = wm0 + 32 * i + l32;
-                const u32x4 x0 = *reinterpret_cast<const u32x4*>(a_hi + pk_slot<UK>(row, (2 * g + h) * UPL) * 16);
-                const u32x4 x1 = *reinterpret_cast<const u32x4*>(a_hi + pk_slot<UK>(row, (2 * g + h) * UPL + 1) * 16);
-                av[i] = i32x8{(int)x0[0], (int)x0[1], (int)x0[2], (int)x0[3],
-                              (int)x1[0], (int)x1[1], (int)x1[2], (int)x1[3]};
+            for (int k = 0; k < (NREAD < NMFMA ? NREAD : NMFMA); ++k) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
             }
-#pragma unroll
-            for (int j = 0; j < CF::TN; ++j) {
-                const int row = wn0 + 32 * j + l32;
-                const u32x4 x0 = *reinterpret_cast<const u32x4*>(b_hi + pk_slot<UK>(row, (2 * g + h) * UPL) * 16);
-                const u32x4 x1 = *reinterpret_cast<const u32x4*>(b_hi + pk_slot<UK>(row, (2 * g + h) * UPL + 1) * 16);
-                bv[j] = i32x8{(int)x0[0], (int)x0[1], (int)x0[2], (int)x0[3],
-                              (int)x1[0], (int)x1[1], (int)x1[2], (int)x1[3]};
-            }
-#pragma unroll
-            for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-                for (int j = 0; j < CF::TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[i], bv[j], acc[i][j],
-                                                                             0, 0, 0, 0, 0, 0);
-        } else {
-            bf16x8 ah[CF::TM], bh[CF::TN];
-            bf16x8 al[CF::MODE == MODE_X3 ? CF::TM : 1], bl[CF::MODE == MODE_X3 ? CF::TN : 1];
-            const int u = 2 * g + h;
-#pragma unroll
-            for (int i = 0; i < CF::TM; ++i) {
-                const int off = pk_slot<UK>(wm0 + 32 * i + l32, u) * 16;
-                ah[i] = *reinterpret_cast<const bf16x8*>(a_hi + off);
-                if (CF::MODE == MODE_X3) al[i] = *reinterpret_cast<const bf16x8*>(a_lo + off);
-            }
-#pragma unroll
-            for (int j = 0; j < CF::TN; ++j) {
-                const int off = pk_slot<UK>(wn0 + 32 * j + l32, u) * 16;
-                bh[j] = *reinterpret_cast<const bf16x8*>(b_hi + off);
-                if (CF::MODE == MODE_X3) bl[j] = *reinterpret_cast<const bf16x8*>(b_lo + off);
-            }
-            if (CF::MODE == MODE_X3) {
-                // small terms first: lo*hi, hi*lo, then hi*hi
-#pragma unroll
-                for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < CF::TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < CF::TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-                for (int j = 0; j < CF::TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
 }
 
 // Scale product of block (row0, col0) for K scale block kb.
+// (row0, col0 and kb are wave-uniform, so the two loads are scalar loads and do
+// not count against vmcnt, which tracks the panel pipeline.)
 __device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int col0, int kb)
 {
     if (row0 >= a.M || col0 >= a.N) return 1.f;  // a block of padding: never stored
-    return a.sA[(int64_t)(row0 / 128) * a.lds_a + kb] * a.sB[(int64_t)kb * a.lds_b + col0 / 128];
+    const int64_t ia = __builtin_amdgcn_readfirstlane((int)((row0 / 128) * a.lds_a + kb));
+    const int64_t ib = __builtin_amdgcn_readfirstlane((int)(kb * a.lds_b + col0 / 128));
+    return a.sA[ia] * a.sB[ib];
 }
 
 template <class CF>
@@ -299,7 +343,10 @@ __global__ void __launch_bounds__(CF::NT) packed_kernel(PackedArgs a)
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
     const TileCoord tc = map_tile(blockIdx.x, a.tiles_m, a.tiles_n, a.group_m, a.xcd_remap);
     const int m0 = tc.tm * CF::BM, n0 = tc.tn * CF::BN;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    // the wave index is uniform; readfirstlane lets the compiler keep it (and the
+    // load offsets and LDS bases derived from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm0 = (wave / CF::WGN) * CF::WTM, wn0 = (wave % CF::WGN) * CF::WTN;
     const int row_bytes = a.Kp * CF::ES;
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
@@ -332,12 +379,18 @@ __global__ void __launch_bounds__(CF::NT) packed_kernel(PackedArgs a)
             load_panel<CF::UK, CF::B_INSTR>(rBl, lane_off, row_bytes, kb, sb + CF::LDS_B, wave);
     };
 
-    issue(0, lds);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
+    constexpr int NS = CF::NS;
+    for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
     int kb_cur = 0;
     for (int s = 0; s < npanel; ++s) {
-        if (s + 1 < npanel) issue(s + 1, lds + ((s + 1) & 1) * CF::LDS_STAGE);
+        // this wave's loads of panel s have landed once at most the loads of the
+        // panels issued after it remain; then the barrier covers every wave's loads
+        // and frees the stage that panel s - 1 occupied
+        if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * CF::LOADS_PER_STAGE>();
+        else wait_vmcnt<0>();
+        __syncthreads();
+        if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
         if (scaled) {
             const int kb = (s * CF::BK) / 128;
             if (s > 0 && kb != kb_cur) {
@@ -354,9 +407,7 @@ __global__ void __launch_bounds__(CF::NT) packed_kernel(PackedArgs a)
                 kb_cur = kb;
             }
         }
-        pk_mma<CF>(lds + (s & 1) * CF::LDS_STAGE, acc, wm0, wn0, lane);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        pk_mma<CF>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
     }
 
     const int h = lane >> 5, l32 = lane & 31;
@@ -389,18 +440,20 @@ struct PSched {
     void (*kernel)(PackedArgs);
 };
 
-#define TG_PSCHED(DT, MODE, BM, BN, BK, WGM, WGN)                                                 \
-    {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN>::LDS_BYTES,                  \
-     PCfg<MODE, BM, BN, BK, WGM, WGN>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN>>}
+#define TG_PSCHED(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                             \
+    {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::LDS_BYTES,              \
+     PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
 
 const PSched kPacked[] = {
-    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4),
-    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2),
-    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 2),
-    TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 64, 2, 4),
-    TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 64, 2, 2),
-    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 2, 4),
-    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2),
+    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4, 2),
+    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 4, 3),
+    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2, 2),
+    TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 64, 2, 4, 2),
+    TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 32, 2, 4, 4),
+    TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 64, 2, 2, 2),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 2, 4, 2),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 64, 2, 4, 4),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2, 2),
 };
 constexpr int kNumPacked = sizeof(kPacked) / sizeof(kPacked[0]);
 

@@ -232,6 +232,13 @@ def schedules(dtype=None):
     return out
 
 
+def schedule_key(sid):
+    """Readable name of a compiled schedule: dtype, tile sizes, wave grid, load width."""
+    i = schedule_info(sid)
+    return (f"sched:{i['dtype']}:{i['BM']}x{i['BN']}x{i['BK']}:{i['WGM']}x{i['WGN']}:"
+            f"vec{i['vec']}")
+
+
 def tile_map(M, N, BM, BN, group_m, xcd_remap):
     T = (-(-M // BM)) * (-(-N // BN))
     tm = (ctypes.c_int32 * T)()
