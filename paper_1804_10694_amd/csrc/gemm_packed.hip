@@ -138,6 +138,11 @@ template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_>
 struct PCfg {
     static constexpr int MODE = MODE_, BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
     static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
+    // waves per SIMD the register allocation must allow: two workgroups per CU
+    // when one workgroup's LDS fits in half of the 160 KB
+    static constexpr int WAVES_PER_EU = (NS_ * (MODE_ == MODE_X3 ? 2 : 1) * (BM_ + BN_) * BK_ *
+                                         ((MODE_ == MODE_FP8) ? 1 : 2) <= 80 * 1024 && WGM_ * WGN_ == 4)
+                                            ? 2 : 1;
     static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
     static constexpr int ES = (MODE == MODE_FP8) ? 1 : 2;
     static constexpr int KU = 16 / ES;                   // k per 16-byte unit
@@ -338,7 +343,7 @@ __device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int 
 }
 
 template <class CF>
-__global__ void __launch_bounds__(CF::NT) packed_kernel(PackedArgs a)
+__global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) packed_kernel(PackedArgs a)
 {
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
     const TileCoord tc = map_tile(blockIdx.x, a.tiles_m, a.tiles_n, a.group_m, a.xcd_remap);
@@ -445,6 +450,11 @@ struct PSched {
      PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
 
 const PSched kPacked[] = {
+    // two workgroups per CU (LDS <= 80 KB), 4 waves each, three stages
+    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 16, 2, 2, 3),
+    TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 128, 32, 2, 2, 3),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 128, 64, 2, 2, 3),
+    // one workgroup per CU, 8 waves
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4, 2),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 4, 3),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2, 2),
