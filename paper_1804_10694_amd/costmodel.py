@@ -21,8 +21,12 @@ Shapes of the study: im2col gemms of 3x3 convolutions, batch 32
 (M = 32 H W, N = Cout, K = 9 Cin) plus log-uniform random shapes.
 
 Command line:
-  python -m paper_1804_10694_amd.costmodel run --out DIR [--random 2000]
-      [--dtype f32] [--reps 5] [--held-out 200] [--epochs 60]
+  python -m paper_1804_10694_amd.costmodel {run|collect|fit} --out DIR
+      [--random 2000] [--dtype f32] [--reps 5] [--held-out 200] [--epochs 60]
+      [--budget SECONDS]
+  collect stops after --budget seconds and resumes on the next call; fit trains
+  and evaluates on what DIR holds; run does both, fitting only once every shape
+  is collected.
 """
 import argparse
 import json
@@ -62,14 +66,50 @@ def by_shape(recs, dtype_code):
     return out
 
 
-def collect(shapes, dtype, db_path, reps=5, progress=None):
+def shapes_done(db_path):
+    """Shapes with at least one record in the database (appended whole, see collect)."""
+    done = set()
+    if not os.path.exists(db_path):
+        return done
+    with open(db_path) as f:
+        for line in f:
+            try:
+                r = json.loads(line)
+            except json.JSONDecodeError:
+                continue
+            done.add((r["dtype"], r["M"], r["N"], r["K"]))
+    return done
+
+
+def collect(shapes, dtype, db_path, reps=5, progress=None, budget_s=None):
+    """Exhaustive autotuning of every shape not yet in db_path.
+
+    Each shape is tuned into a temporary file which is appended to db_path only
+    when the shape is complete, so the database holds whole shapes and a killed
+    or budget-stopped run resumes at the first missing one.  Returns the number
+    of shapes still missing.
+    """
     tg = _tg()
+    code = tg.DTYPES[dtype]
+    done = shapes_done(db_path)
+    todo = [s for s in dict.fromkeys(tuple(int(x) for x in s) for s in shapes)
+            if (code, *s) not in done]
+    tmp = db_path + ".shape"
     t0 = time.time()
-    for i, (m, n, k) in enumerate(shapes):
-        tg.autotune(int(m), int(n), int(k), dtype, reps, db_path)
+    for i, (m, n, k) in enumerate(todo):
+        if budget_s is not None and time.time() - t0 > budget_s:
+            print(f"collect {dtype}: budget reached, {len(todo) - i} shapes left", flush=True)
+            return len(todo) - i
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        tg.autotune(m, n, k, dtype, reps, tmp)
+        with open(tmp) as f, open(db_path, "a") as g:
+            g.write(f.read())
+        os.remove(tmp)
         if progress and (i + 1) % progress == 0:
-            print(f"collect {dtype}: {i + 1}/{len(shapes)} shapes, {time.time() - t0:.0f} s",
+            print(f"collect {dtype}: {i + 1}/{len(todo)} shapes, {time.time() - t0:.0f} s",
                   flush=True)
+    return 0
 
 
 def split(shapes, held_out, seed=5):
@@ -152,7 +192,7 @@ def study_shapes(n_random, seed=5, lo=64, hi=8192):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["run"])
+    ap.add_argument("cmd", choices=["run", "collect", "fit"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--random", type=int, default=2000)
     ap.add_argument("--hi", type=int, default=8192)
@@ -160,14 +200,17 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--held-out", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--no-collect", action="store_true")
+    ap.add_argument("--budget", type=float, default=None, help="collection time limit, seconds")
     args = ap.parse_args()
     tg = _tg()
     os.makedirs(args.out, exist_ok=True)
     db = os.path.join(args.out, f"tune_{args.dtype}.jsonl")
     shapes = study_shapes(args.random, hi=args.hi)
-    if not args.no_collect:
-        collect(shapes, args.dtype, db, args.reps, progress=50)
+    if args.cmd in ("run", "collect"):
+        left = collect(shapes, args.dtype, db, args.reps, progress=50, budget_s=args.budget)
+        print(json.dumps({"dtype": args.dtype, "shapes": len(set(shapes)), "left": left}), flush=True)
+        if args.cmd == "collect" or left:
+            return
     train, held = split(shapes, args.held_out)
     tdb = os.path.join(args.out, f"train_{args.dtype}.jsonl")
     n_train = subset(db, train, tdb)

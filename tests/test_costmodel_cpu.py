@@ -54,3 +54,37 @@ def test_train_rejects_bad_arguments(tg, tmp_path):
     assert tg.lib.tgemm_costmodel_train(db, w, 0, 64, 1e-3, 1, None) == tg.INVALID_VALUE
     assert tg.lib.tgemm_costmodel_train(db, w, 5, 64, -1.0, 1, None) == tg.INVALID_VALUE
     assert tg.lib.tgemm_costmodel_train(db, w, 5, 64, 1e-3, 1, None) == tg.INVALID_VALUE  # no file
+
+
+def test_collection_appends_whole_shapes_and_resumes(tmp_path, monkeypatch):
+    """collect() writes a shape to the database only once it is tuned whole, stops at its
+    time budget and resumes at the first missing shape (autotuning replaced by a stub)."""
+    import json
+    from paper_1804_10694_amd import costmodel as CM
+
+    calls = []
+
+    class Stub:
+        DTYPES = {"f32": 0}
+
+        @staticmethod
+        def autotune(m, n, k, dtype, reps, db):
+            calls.append((m, n, k))
+            with open(db, "a") as f:
+                for sid in range(3):
+                    f.write(json.dumps({"dtype": 0, "M": m, "N": n, "K": k, "sched": sid,
+                                        "group_m": 1, "xcd": 0, "ms": 1.0 + sid,
+                                        "valid": True}) + "\n")
+
+    monkeypatch.setattr(CM, "_tg", lambda: Stub)
+    db = str(tmp_path / "db.jsonl")
+    shapes = [(64, 64, 64), (128, 64, 64), (64, 64, 64), (256, 128, 64)]
+    assert CM.collect(shapes, "f32", db, budget_s=-1.0) == 3      # budget spent before the first
+    assert calls == []
+    assert CM.collect(shapes[:2], "f32", db) == 0
+    assert CM.collect(shapes, "f32", db) == 0                     # only the missing shape is tuned
+    assert calls == [(64, 64, 64), (128, 64, 64), (256, 128, 64)]
+    recs = CM.read_db(db)
+    assert len(recs) == 9 and CM.shapes_done(db) == {(0, 64, 64, 64), (0, 128, 64, 64),
+                                                     (0, 256, 128, 64)}
+    assert not (tmp_path / "db.jsonl.shape").exists()
