@@ -21,7 +21,8 @@ the path on their own workloads:
     seed 30), quantised on the GPU, e4m3 and bf16, alpha = 1, beta = 0;
   - the grouped persistent launch over 512 problems with M, N, K log-uniform in
     [16, 2048] (seed 4, matrices from seeds 4000 + p), alpha = 1, beta = 0.5,
-    F32 and split-bf16x3, replayed from a HIP graph.
+    F32 and split-bf16x3, tile shapes tuned on the set (tgemm_batched_autotune),
+    replayed from a HIP graph.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-extras]
@@ -167,6 +168,7 @@ def extra_rows(tg, inputs):
     gbytes = float(sum(4.0 * (m * k + k * n_ + 2 * m * n_) for m, n_, k in dims))
     for dt in ("f32", "x3"):
         al, be = [1.0] * len(dims), [0.5] * len(dims)
+        threshold = tg.gemm_batched_autotune(As, Bs, Cs, al, be, dt, reps=5)   # tile shapes
         tg.gemm_batched(As, Bs, Cs, al, be, dt)          # plans
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
@@ -180,6 +182,7 @@ def extra_rows(tg, inputs):
             "tflops": round(gflops / (avg * 1e-3) / 1e12, 2),
             "hbm_gbs_compulsory": round(gbytes / (avg * 1e-3) / 1e9, 1),
             "floor_ms": round(floor_ms, 4), "frac_of_floor": round(floor_ms / avg, 4),
+            "tile128_threshold": threshold,
             "bound": "mfma" if gflops / (PEAK_TFLOPS[dt] * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
             else "hbm"}
         del graph

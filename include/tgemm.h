@@ -125,7 +125,10 @@ int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx
  * problem set (dimensions, leading dimensions, pointers, alpha, beta, dtype)
  * chooses a schedule per problem, builds the tile index space and uploads a
  * descriptor table to device memory owned by the library; later calls with
- * the same set launch one kernel.  If `stream` is capturing and the set has
+ * the same set launch one kernel.  The tile shape of a problem is 128 x 128
+ * when both M and N reach a threshold, 64 x 64 otherwise: the threshold
+ * tgemm_batched_autotune measured for sets of these dimensions, else 96.
+ * If `stream` is capturing and the set has
  * no plan yet, the call returns TGEMM_CAPTURE_UNPLANNED: call once outside
  * capture first.  dtype: TGEMM_F32 or TGEMM_F32_BF16X3.
  */
@@ -133,6 +136,28 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
                   const float* alpha, const void* const* A, const int64_t* lda,
                   const void* const* B, const int64_t* ldb, const float* beta,
                   float* const* C, const int64_t* ldc, int dtype, void* stream);
+
+/*
+ * Tile-shape autotuner of the grouped launch (project addition; the paper
+ * chooses tile sizes by measurement, Section VI-A).  Same arguments as
+ * tgemm_batched plus `reps`.  A problem gets 128 x 128 macro-tiles when both
+ * its M and N reach a threshold T, 64 x 64 otherwise; the tuner times one
+ * launch of the whole set for each T in {0, 64, 96, 160, 256, 512, never}
+ * (thresholds that assign every problem the same tiles are timed once),
+ * takes the median of `reps` timed launches after one warm-up, and keeps the
+ * fastest T for problem sets of these dimensions (M, N, K, alpha == 0 and
+ * load width per problem).  Later tgemm_batched calls on such sets use it;
+ * cached plans of these dimensions are discarded, so a graph captured over
+ * one must be captured again.  C is restored to its contents at entry
+ * (the timed launches overwrite it; a device copy of C is allocated for
+ * the call).  Synchronises `stream`.  Not allowed while `stream` captures.
+ * Returns the threshold chosen (>= 0; INT32_MAX means 64 x 64 everywhere)
+ * or -status.  reps in [1, 1000].
+ */
+int tgemm_batched_autotune(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                           const float* alpha, const void* const* A, const int64_t* lda,
+                           const void* const* B, const int64_t* ldb, const float* beta,
+                           float* const* C, const int64_t* ldc, int dtype, int reps, void* stream);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* tgemm_status_string(int status);

@@ -4,7 +4,11 @@
 // of uneven gemms).
 //
 // Plan (host, once per problem set): every problem gets a tile configuration
-// (macro-tile size and global-load width); problems are ordered by the work of
+// (macro-tile size and global-load width): 128 x 128 macro-tiles when both M
+// and N reach a threshold, 64 x 64 otherwise.  The threshold is a built-in
+// default unless tgemm_batched_autotune has measured the problem set's
+// dimensions, in which case the fastest threshold it timed is used.
+// Problems are ordered by the work of
 // one of their tiles, largest first, and their tile counts are prefix-summed
 // into one tile index space; a descriptor table and the prefix sums are
 // uploaded to device memory the plan owns.  Launch: grid = the number of
@@ -132,6 +136,7 @@ namespace {
 
 struct Plan {
     std::vector<uint64_t> key;
+    uint64_t dims = 0;  // dims_key of the set
     int dtype = 0;
     int count = 0;   // problems with at least one tile
     int total = 0;   // tiles
@@ -162,18 +167,25 @@ uint64_t fbits(float f)
     return u;
 }
 
-int choose_cfg(const GroupDesc& g, bool vec)
+// Default threshold: 128 x 128 macro-tiles once both output dimensions fill
+// most of one (fewer, more efficient tiles); 64 x 64 otherwise (less padding).
+constexpr int kDefaultThreshold = 96;
+// Thresholds the tuner times; the last one means "64 x 64 everywhere".
+constexpr int kThresholds[] = {0, 64, 96, 160, 256, 512, INT32_MAX};
+
+int choose_cfg(const GroupDesc& g, bool vec, int threshold)
 {
-    // 128 x 128 macro-tiles once both output dimensions fill most of one
-    // (fewer, more efficient tiles); 64 x 64 otherwise (less padding waste).
-    const bool big = g.M >= 96 && g.N >= 96;
+    const bool big = g.M >= threshold && g.N >= threshold;
     return (big ? 2 : 0) + (vec ? 0 : 1);
 }
+
+// Tuned thresholds by problem-set dimensions (pointers, alpha and beta left out).
+std::map<uint64_t, int> g_tuned_threshold;
 
 int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                const float* alpha, const void* const* A, const int64_t* lda, const void* const* B,
                const int64_t* ldb, const float* beta, float* const* C, const int64_t* ldc, int dtype,
-               Plan* plan)
+               int threshold, Plan* plan)
 {
     std::vector<GroupDesc> descs;
     for (int64_t p = 0; p < count; ++p) {
@@ -192,7 +204,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         g.alpha = alpha[p];
         g.beta = beta[p];
         g.scale_only = (K[p] == 0 || alpha[p] == 0.f) ? 1 : 0;
-        g.cfg = g.scale_only ? 0 : choose_cfg(g, vec_ok(A[p], lda[p], B[p], ldb[p], dtype));
+        g.cfg = g.scale_only ? 0 : choose_cfg(g, vec_ok(A[p], lda[p], B[p], ldb[p], dtype), threshold);
         const int t = kGroupTile[g.cfg];
         g.tiles_m = (int)((M[p] + t - 1) / t);
         g.tiles_n = (int)((N[p] + t - 1) / t);
@@ -249,16 +261,22 @@ void free_plan(Plan& p)
     p.d_prefix = nullptr;
 }
 
-}  // namespace
-
-}  // namespace tg
-
-extern "C" int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
-                             const float* alpha, const void* const* A, const int64_t* lda,
-                             const void* const* B, const int64_t* ldb, const float* beta,
-                             float* const* C, const int64_t* ldc, int dtype, void* stream)
+int launch_plan(const Plan& p, hipStream_t s)
 {
-    using namespace tg;
+    if (p.count == 0) return TGEMM_SUCCESS;
+    if (p.dtype == TGEMM_F32)
+        hipLaunchKernelGGL(grouped_kernel<MODE_F32>, dim3(p.grid), dim3(256), 0, s, p.d_desc,
+                           p.d_prefix, p.count, p.total);
+    else
+        hipLaunchKernelGGL(grouped_kernel<MODE_X3>, dim3(p.grid), dim3(256), 0, s, p.d_desc,
+                           p.d_prefix, p.count, p.total);
+    return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+}
+
+int validate_set(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                 const float* alpha, const void* const* A, const int64_t* lda, const void* const* B,
+                 const int64_t* ldb, const float* beta, float* const* C, const int64_t* ldc, int dtype)
+{
     if (dtype != TGEMM_F32 && dtype != TGEMM_F32_BF16X3) return TGEMM_NOT_SUPPORTED;
     if (count < 0 || count > (1 << 24)) return TGEMM_INVALID_VALUE;
     if (count == 0) return TGEMM_SUCCESS;
@@ -269,6 +287,40 @@ extern "C" int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, 
                                      C[p], ldc[p], dtype);
         if (rc != TGEMM_SUCCESS) return rc;
     }
+    return TGEMM_SUCCESS;
+}
+
+// Key of the dimensions alone: what the tile configuration depends on.
+uint64_t dims_key(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                  const float* alpha, const void* const* A, const int64_t* lda, const void* const* B,
+                  const int64_t* ldb, int dtype)
+{
+    std::vector<uint64_t> v;
+    v.reserve((size_t)count * 5 + 2);
+    v.push_back((uint64_t)count);
+    v.push_back((uint64_t)dtype);
+    for (int64_t p = 0; p < count; ++p) {
+        v.push_back((uint64_t)M[p]);
+        v.push_back((uint64_t)N[p]);
+        v.push_back((uint64_t)K[p]);
+        v.push_back(alpha[p] == 0.f ? 1u : 0u);
+        v.push_back(vec_ok(A[p], lda[p], B[p], ldb[p], dtype) ? 1u : 0u);
+    }
+    return fnv(v);
+}
+
+}  // namespace
+
+}  // namespace tg
+
+extern "C" int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                             const float* alpha, const void* const* A, const int64_t* lda,
+                             const void* const* B, const int64_t* ldb, const float* beta,
+                             float* const* C, const int64_t* ldc, int dtype, void* stream)
+{
+    using namespace tg;
+    int rc = validate_set(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (rc != TGEMM_SUCCESS || count == 0) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     // key of the problem set
@@ -299,30 +351,133 @@ extern "C" int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, 
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
             return TGEMM_CAPTURE_UNPLANNED;
-        int rc = ensure_device(s);
+        rc = ensure_device(s);
         if (rc != TGEMM_SUCCESS) return rc;
         if (it != g_plans.end()) {
             free_plan(it->second);
             g_plans.erase(it);
         }
+        const uint64_t dk = dims_key(count, M, N, K, alpha, A, lda, B, ldb, dtype);
+        auto tuned = g_tuned_threshold.find(dk);
+        const int threshold = tuned != g_tuned_threshold.end() ? tuned->second : kDefaultThreshold;
         Plan plan;
         plan.key = key;
-        rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, &plan);
+        plan.dims = dk;
+        rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, threshold, &plan);
         if (rc != TGEMM_SUCCESS) {
             free_plan(plan);
             return rc;
         }
         it = g_plans.emplace(h, std::move(plan)).first;
     }
-    const Plan& p = it->second;
-    if (p.count == 0) return TGEMM_SUCCESS;
-    if (dtype == TGEMM_F32)
-        hipLaunchKernelGGL(grouped_kernel<MODE_F32>, dim3(p.grid), dim3(256), 0, s, p.d_desc,
-                           p.d_prefix, p.count, p.total);
-    else
-        hipLaunchKernelGGL(grouped_kernel<MODE_X3>, dim3(p.grid), dim3(256), 0, s, p.d_desc,
-                           p.d_prefix, p.count, p.total);
-    return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+    return launch_plan(it->second, s);
+}
+
+extern "C" int tgemm_batched_autotune(int64_t count, const int64_t* M, const int64_t* N,
+                                      const int64_t* K, const float* alpha, const void* const* A,
+                                      const int64_t* lda, const void* const* B, const int64_t* ldb,
+                                      const float* beta, float* const* C, const int64_t* ldc,
+                                      int dtype, int reps, void* stream)
+{
+    using namespace tg;
+    if (reps < 1 || reps > 1000) return -TGEMM_INVALID_VALUE;
+    int rc = validate_set(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (rc != TGEMM_SUCCESS) return -rc;
+    if (count == 0) return kDefaultThreshold;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return -TGEMM_CAPTURE_UNPLANNED;
+    rc = ensure_device(s);
+    if (rc != TGEMM_SUCCESS) return -rc;
+
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    // The timed launches overwrite C: keep a copy and put it back at the end.
+    int64_t total = 0;
+    for (int64_t p = 0; p < count; ++p) total += M[p] * N[p];
+    float* saved = nullptr;
+    if (total > 0 && hipMalloc(&saved, (size_t)total * sizeof(float)) != hipSuccess)
+        return -TGEMM_ALLOC_FAILED;
+    auto copy_c = [&](bool save) {
+        int64_t off = 0;
+        for (int64_t p = 0; p < count; ++p) {
+            if (M[p] == 0 || N[p] == 0) continue;
+            float* packed = saved + off;
+            const size_t w = (size_t)N[p] * sizeof(float);
+            const hipError_t e =
+                save ? hipMemcpy2DAsync(packed, w, C[p], (size_t)ldc[p] * sizeof(float), w, (size_t)M[p],
+                                        hipMemcpyDeviceToDevice, s)
+                     : hipMemcpy2DAsync(C[p], (size_t)ldc[p] * sizeof(float), packed, w, w, (size_t)M[p],
+                                        hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return false;
+            off += M[p] * N[p];
+        }
+        return true;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0.f;
+    std::vector<std::vector<int>> seen;  // configuration vectors already timed
+    rc = copy_c(true) ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+    for (int threshold : kThresholds) {
+        if (rc != TGEMM_SUCCESS) break;
+        Plan plan;
+        rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, threshold, &plan);
+        if (rc != TGEMM_SUCCESS) {
+            free_plan(plan);
+            break;
+        }
+        // thresholds that give the same configuration for every problem are timed once
+        std::vector<int> cfgs;
+        for (int64_t p = 0; p < count; ++p)
+            cfgs.push_back(M[p] >= threshold && N[p] >= threshold ? 1 : 0);
+        if (std::find(seen.begin(), seen.end(), cfgs) != seen.end()) {
+            free_plan(plan);
+            continue;
+        }
+        seen.push_back(cfgs);
+        std::vector<float> times;
+        rc = launch_plan(plan, s);  // warm-up
+        for (int r = 0; r < reps && rc == TGEMM_SUCCESS; ++r) {
+            (void)hipEventRecord(e0, s);
+            rc = launch_plan(plan, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = TGEMM_LAUNCH_FAILED;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            times.push_back(ms);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess && rc == TGEMM_SUCCESS) rc = TGEMM_LAUNCH_FAILED;
+        free_plan(plan);
+        if (rc != TGEMM_SUCCESS) break;
+        std::sort(times.begin(), times.end());
+        const float med = times[times.size() / 2];
+        if (best < 0 || med < best_ms) {
+            best = threshold;
+            best_ms = med;
+        }
+    }
+    if (rc == TGEMM_SUCCESS && !copy_c(false)) rc = TGEMM_LAUNCH_FAILED;
+    if (hipStreamSynchronize(s) != hipSuccess && rc == TGEMM_SUCCESS) rc = TGEMM_LAUNCH_FAILED;
+    if (saved) (void)hipFree(saved);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TGEMM_SUCCESS) return -rc;
+    const uint64_t dk = dims_key(count, M, N, K, alpha, A, lda, B, ldb, dtype);
+    g_tuned_threshold[dk] = best;
+    // plans of these dimensions built before the tuning are rebuilt with the
+    // tuned threshold on next use
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (it->second.dims == dk) {
+            free_plan(it->second);
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return best;
 }
 
 extern "C" void tgemm_shutdown(void)
@@ -331,5 +486,6 @@ extern "C" void tgemm_shutdown(void)
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto& kv : g_plans) free_plan(kv.second);
     g_plans.clear();
+    g_tuned_threshold.clear();
     packed_shutdown();
 }

@@ -1,12 +1,13 @@
-// Packed-operand gemm for the 16- and 8-bit MFMA forms (split-bf16x3, bf16 and
-// e4m3 with per-tile scales).
+// Packed-operand gemm for every MFMA form: f32, split-bf16x3, and bf16 and
+// e4m3 with per-tile scales.
 //
 // Array packing (Tiramisu paper, Section I, after Goto and van de Geijn) as a
 // pre-pass: A (M x K, row-major) and B (K x N, row-major) are copied once into
 // packed buffers whose rows are K-contiguous, in the element type the MFMA
 // reads, zero-padded to multiples of kPackRows rows and kPackK columns:
 //   Ap[m][k]  = conv(A[m][k]),   Bp[n][k] = conv(B[k][n])   (B transposed)
-// where conv is the x3 split (two arrays, hi and lo) or a plain copy of codes.
+// where conv is the x3 split (two arrays, hi and lo) or a plain copy of the
+// values (f32) or codes (bf16, e4m3).
 // The padding turns every tile into a full tile for the loads, so the main
 // kernel's K loop carries no predicates; the full/partial distinction of
 // Section V-C remains only in the epilogue (masked stores for edge tiles).
@@ -45,7 +46,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // ------------------------------------------------------------------ packing
 // A-side: rows of X (R x K, row stride ldx) -> P (Rp x Kp), 8 consecutive
 // k per thread.  x3: X is float, P / Plo receive the bf16 hi and lo parts.
-// bf16 / e4m3: X holds codes of ES bytes, copied.
+// f32: floats, copied.  bf16 / e4m3: X holds codes of ES bytes, copied.
 template <int MODE>
 __global__ void pack_rows_kernel(const void* X, int64_t ldx, int R, int K, void* P, void* Plo,
                                  int Rp, int Kp)
@@ -55,7 +56,19 @@ __global__ void pack_rows_kernel(const void* X, int64_t ldx, int R, int K, void*
          gi += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(gi / (Kp / 8));
         const int k0 = (int)(gi % (Kp / 8)) * 8;
-        if (MODE == MODE_X3) {
+        if (MODE == MODE_F32) {
+            f32x4 v0, v1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = (r < R && k0 + e < K)
+                                    ? static_cast<const float*>(X)[(int64_t)r * ldx + k0 + e] : 0.f;
+                if (e < 4) v0[e] = v;
+                else v1[e - 4] = v;
+            }
+            float* dst = static_cast<float*>(P) + (int64_t)r * Kp + k0;
+            *reinterpret_cast<f32x4*>(dst) = v0;
+            *reinterpret_cast<f32x4*>(dst + 4) = v1;
+        } else if (MODE == MODE_X3) {
             bf16x8 h, l;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -107,7 +120,7 @@ __global__ void __launch_bounds__(256) pack_cols_kernel(const void* X, int64_t l
         const int k = k0 + kk, n = n0 + tx;
         float v = 0.f;
         if (k < K && n < N) {
-            if (MODE == MODE_X3) v = static_cast<const float*>(X)[(int64_t)k * ldx + n];
+            if (MODE == MODE_X3 || MODE == MODE_F32) v = static_cast<const float*>(X)[(int64_t)k * ldx + n];
             else if (MODE == MODE_BF16)
                 v = __uint_as_float(static_cast<const uint16_t*>(X)[(int64_t)k * ldx + n]);
             else v = __uint_as_float(static_cast<const uint8_t*>(X)[(int64_t)k * ldx + n]);
@@ -120,7 +133,9 @@ __global__ void __launch_bounds__(256) pack_cols_kernel(const void* X, int64_t l
         if (n >= Np || k >= Kp) continue;
         const float v = tile[tx][nn];
         const int64_t o = (int64_t)n * Kp + k;
-        if (MODE == MODE_X3) {
+        if (MODE == MODE_F32) {
+            static_cast<float*>(P)[o] = v;
+        } else if (MODE == MODE_X3) {
             __bf16 hh, ll;
             split_bf16(v, hh, ll);
             static_cast<__bf16*>(P)[o] = hh;
@@ -140,15 +155,16 @@ struct PCfg {
     static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
     // waves per SIMD the register allocation must allow: two workgroups per CU
     // when one workgroup's LDS fits in half of the 160 KB
-    static constexpr int WAVES_PER_EU = (NS_ * (MODE_ == MODE_X3 ? 2 : 1) * (BM_ + BN_) * BK_ *
-                                         ((MODE_ == MODE_FP8) ? 1 : 2) <= 80 * 1024 && WGM_ * WGN_ == 4)
-                                            ? 2 : 1;
+    static constexpr int ES = (MODE == MODE_FP8) ? 1 : (MODE == MODE_F32) ? 4 : 2;  // bytes
+    static constexpr int WAVES_PER_EU =
+        (NS_ * (MODE_ == MODE_X3 ? 2 : 1) * (BM_ + BN_) * BK_ * ES <= 80 * 1024 && WGM_ * WGN_ == 4) ? 2 : 1;
     static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
-    static constexpr int ES = (MODE == MODE_FP8) ? 1 : 2;
     static constexpr int KU = 16 / ES;                   // k per 16-byte unit
     static constexpr int UK = BK / KU;                   // units per packed row per panel
-    static constexpr int MK = (MODE == MODE_FP8) ? 64 : 16;
-    static constexpr int UPL = MK / KU / 2;              // units per lane per MFMA
+    // k per MFMA group: 32x32x64 e4m3, 32x32x16 bf16; f32 runs the four
+    // 32x32x2 MFMAs of one unit per lane as a group of 8 k
+    static constexpr int MK = (MODE == MODE_FP8) ? 64 : (MODE == MODE_F32) ? 8 : 16;
+    static constexpr int UPL = MK / KU / 2;              // units per lane per group
     static constexpr int NG = BK / MK;
     static constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 32, TN = WTN / 32;
     static constexpr int NARR = (MODE == MODE_X3) ? 2 : 1;
@@ -263,7 +279,19 @@ __device__ __forceinline__ void pk_load(const char* stage, PkOps<CF>& o, int g, 
 template <class CF>
 __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN])
 {
-    if (CF::MODE == MODE_FP8) {
+    if (CF::MODE == MODE_F32) {
+        // element e of a lane's unit is k = 4*(2g + lane/32) + e for both
+        // operands, so MFMA e pairs equal k in A and B
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                        __builtin_bit_cast(float, o.a[0][i][0][e]), __builtin_bit_cast(float, o.b[0][j][0][e]),
+                        acc[i][j], 0, 0, 0);
+    } else if (CF::MODE == MODE_FP8) {
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
@@ -313,7 +341,7 @@ __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][
                                        int wn0, int lane)
 {
     constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
-    constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : 1);
+    constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
     PkOps<CF> ops[2];
     pk_load<CF>(stage, ops[0], 0, wm0, wn0, lane);
 #pragma unroll
@@ -362,7 +390,7 @@ __global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) packed_kernel(Packed
         rBl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
     }
     const int lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
-    const bool scaled = (CF::MODE != MODE_X3) && a.sA;
+    const bool scaled = (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA;
 
     f32x16 acc[CF::TM][CF::TN];
 #pragma unroll
@@ -450,11 +478,16 @@ struct PSched {
      PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
 
 const PSched kPacked[] = {
-    // two workgroups per CU (LDS <= 80 KB), 4 waves each, three stages
+    // two workgroups per CU (LDS <= 80 KB), 4 waves each
+    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 32, 2, 2, 2),
+    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 4),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 16, 2, 2, 3),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 128, 32, 2, 2, 3),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 128, 64, 2, 2, 3),
     // one workgroup per CU, 8 waves
+    TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 32, 2, 4, 2),
+    TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 16, 2, 4, 4),
+    TG_PSCHED(TGEMM_F32, MODE_F32, 256, 128, 32, 2, 4, 3),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4, 2),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 4, 3),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2, 2),
@@ -503,7 +536,7 @@ size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype)
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
-    const int64_t es = dtype == TGEMM_FP8_E4M3 ? 1 : 2;
+    const int64_t es = dtype == TGEMM_FP8_E4M3 ? 1 : dtype == TGEMM_F32 ? 4 : 2;
     const int64_t arrays = dtype == TGEMM_F32_BF16X3 ? 2 : 1;
     return (size_t)((Mp + Np) * Kp * es * arrays);
 }
@@ -556,7 +589,7 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
-    const int64_t es = p.dtype == TGEMM_FP8_E4M3 ? 1 : 2;
+    const int64_t es = p.dtype == TGEMM_FP8_E4M3 ? 1 : p.dtype == TGEMM_F32 ? 4 : 2;
     char* base = static_cast<char*>(ws);
     char* Ap = base;
     char* Alo = p.mode == MODE_X3 ? Ap + Mp * Kp * es : nullptr;
@@ -567,6 +600,12 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     const unsigned ga = (unsigned)std::min<int64_t>((groups_a + 255) / 256, 65536);
     const dim3 gb((unsigned)(Np / 64), (unsigned)(Kp / 64));
     switch (p.mode) {
+        case MODE_F32:
+            hipLaunchKernelGGL(pack_rows_kernel<MODE_F32>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
+                               (int)K, Ap, nullptr, (int)Mp, (int)Kp);
+            hipLaunchKernelGGL(pack_cols_kernel<MODE_F32>, gb, dim3(256), 0, s, B, ldb, (int)K, (int)N,
+                               Bp, nullptr, (int)Np, (int)Kp);
+            break;
         case MODE_X3:
             hipLaunchKernelGGL(pack_rows_kernel<MODE_X3>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
                                (int)K, Ap, Alo, (int)Mp, (int)Kp);

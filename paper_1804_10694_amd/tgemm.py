@@ -38,6 +38,8 @@ lib.tgemm_scaled.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _p, _i64, _p,
 lib.tgemm_quantize_tiles.argtypes = [_i64, _i64, _p, _i64, _p, _i64, _p, _i32, _p]
 lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32, _pp,
                               _pi64, _i32, _p]
+lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
+                                       _pp, _pi64, _i32, _i32, _p]
 lib.tgemm_status_string.argtypes = [_i32]
 lib.tgemm_status_string.restype = ctypes.c_char_p
 lib.tgemm_set_policy.argtypes = [ctypes.c_char_p]
@@ -189,6 +191,11 @@ def _arr(ctype, values):
 
 def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None):
     """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p."""
+    rc = lib.tgemm_batched(*_batched_args(As, Bs, Cs, alphas, betas, dtype), _stream_handle(stream))
+    _check(rc, "tgemm_batched")
+
+
+def _batched_args(As, Bs, Cs, alphas, betas, dtype):
     dt = _dtype_code(dtype)
     n = len(As)
     Ms, Ns, Ks, pa, pb, pc, la, lb, lc = [], [], [], [], [], [], [], [], []
@@ -201,11 +208,19 @@ def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None):
         Ms.append(M); Ns.append(N); Ks.append(K)
         pa.append(a); pb.append(b); pc.append(c)
         la.append(lda); lb.append(ldb); lc.append(ldc)
-    rc = lib.tgemm_batched(n, _arr(_i64, Ms), _arr(_i64, Ns), _arr(_i64, Ks),
-                           _arr(_f32, list(alphas)), _arr(_p, pa), _arr(_i64, la), _arr(_p, pb),
-                           _arr(_i64, lb), _arr(_f32, list(betas)), _arr(_p, pc), _arr(_i64, lc),
-                           dt, _stream_handle(stream))
-    _check(rc, "tgemm_batched")
+    return (n, _arr(_i64, Ms), _arr(_i64, Ns), _arr(_i64, Ks), _arr(_f32, list(alphas)),
+            _arr(_p, pa), _arr(_i64, la), _arr(_p, pb), _arr(_i64, lb), _arr(_f32, list(betas)),
+            _arr(_p, pc), _arr(_i64, lc), dt)
+
+
+def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream=None):
+    """Tile-shape tuning of a grouped set (tgemm_batched_autotune); returns the
+    128x128-tile threshold chosen (2**31 - 1: 64x64 tiles everywhere)."""
+    args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
+    rc = lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream))
+    if rc < 0:
+        raise TgemmError(-rc, "tgemm_batched_autotune")
+    return rc
 
 
 def set_policy(policy):

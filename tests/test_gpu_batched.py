@@ -159,3 +159,38 @@ def test_batched_validation(tg):
                                   arr(p, [A.data_ptr()]), arr(i64, [8]), arr(ctypes.c_float, [0.0]),
                                   arr(p, [A.data_ptr()]), arr(i64, [8]), 0, None)
     assert bad_ld == tg.INVALID_VALUE
+
+
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_autotune_restores_c_and_tuned_plan_is_exact(tg, dtype):
+    # The tile-shape tuner times whole-set launches (which overwrite C), puts C back,
+    # and later grouped calls use the tuned threshold: still bit-exact on integers.
+    rng = np.random.default_rng(53)
+    dims = rng.integers(16, 400, size=(40, 3))
+    dims[0] = (300, 260, 70)     # 128-tile candidate with edges
+    dims[1] = (40, 500, 33)      # 64 tiles under every threshold above 40
+    host = _problem_set(dims, 5300, integer=True)
+    alphas = [1.0] * len(dims)
+    betas = [0.5] * len(dims)
+    As = [h[0].to(DEV) for h in host]
+    Bs = [h[1].to(DEV) for h in host]
+    Cs = [h[2].clone().to(DEV) for h in host]
+    before = [c.clone() for c in Cs]
+    t = tg.gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype, reps=2)
+    torch.cuda.synchronize()
+    print(f"{dtype}: tuned threshold {t}", flush=True)
+    assert t in (0, 64, 96, 160, 256, 512, 2**31 - 1)
+    for p, (b, c) in enumerate(zip(before, Cs)):
+        assert torch.equal(b, c), f"C of problem {p} not restored"
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
+    torch.cuda.synchronize()
+    for p, h in enumerate(host):
+        ref = oracle.gemm(h[0], h[1], h[2], alphas[p], betas[p])
+        np.testing.assert_array_equal(Cs[p].cpu().numpy().astype(np.float64), ref,
+                                      err_msg=f"problem {p} {dims[p]}")
+
+
+def test_autotune_rejects_bad_reps(tg):
+    A = torch.ones(8, 8, device=DEV)
+    with pytest.raises(tg.TgemmError):
+        tg.gemm_batched_autotune([A], [A], [A.clone()], [1.0], [0.0], "f32", reps=0)
