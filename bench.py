@@ -70,7 +70,8 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel_symbol):
-    """HBM bytes per launch of `kernel_symbol` from the committed counter summary, or None
+    """HBM bytes per call of `kernel_symbol` ("schedule key@MxNxK") from the committed counter
+    summary (written by paper_1804_10694_amd.profsum), or None
     when there is none or the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
@@ -245,20 +246,31 @@ def main():
         avg = sum(times) / len(times)
         med = times[len(times) // 2]
         tf = flops(s) / (avg * 1e-3) / 1e12
+        sched = tg.select_schedule(*s, dt)
+        info = tg.schedule_info(sched[0])
+        tiles = -(-s[0] // info["BM"]) * -(-s[1] // info["BN"])
         per_path[f"{dt}_{s[0]}x{s[1]}x{s[2]}"] = {
             "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(tf, 2),
             "peak_tflops": round(PEAK_TFLOPS[dt], 1), "frac_peak": round(tf / PEAK_TFLOPS[dt], 4),
-            "schedule": tg.select_schedule(*s, dt)}
+            "schedule": sched, "schedule_key": tg.schedule_key(sched[0]),
+            "packed": info["vec"] == 0,
+            # threads of the main kernel's grid: how a profile tells the paths apart
+            "grid_threads": tiles * 64 * info["WGM"] * info["WGN"]}
 
     # dominant kernel = the path with the largest share of the step
     dom_key = max(per_path, key=lambda k: per_path[k]["avg_ms"])
     dom = per_path[dom_key]
     dt_dom, shape_dom = [p for p in paths if f"{p[0]}_{p[1][0]}x{p[1][1]}x{p[1][2]}" == dom_key][0]
-    sym = tg.schedule_key(tg.select_schedule(*shape_dom, dt_dom)[0])
-    roofline = {"bound": "mfma", "kernel": dom_key, "kernel_symbol": sym, "achieved": dom["tflops"],
+    sym = f"{dom['schedule_key']}@{shape_dom[0]}x{shape_dom[1]}x{shape_dom[2]}"
+    # a packed schedule's call is three kernels (A packing, B packing, main kernel);
+    # the events, and so `achieved`, cover the whole call
+    roofline = {"bound": "mfma", "kernel": dom_key, "kernel_symbol": sym,
+                "kernels_per_call": (["pack_rows_kernel", "pack_cols_kernel", "packed_kernel"]
+                                     if dom["packed"] else ["gemm_kernel"]),
+                "achieved": dom["tflops"],
                 "peak": dom["peak_tflops"], "unit": "TFLOP/s",
                 "frac": round(dom["tflops"] / dom["peak_tflops"], 4),
-                "traffic": measured_traffic(sym), "traffic_unit": "bytes per launch",
+                "traffic": measured_traffic(sym), "traffic_unit": "HBM bytes per call",
                 "compulsory_bytes": 4 * (shape_dom[0] * shape_dom[2] + shape_dom[2] * shape_dom[1]
                                          + 2 * shape_dom[0] * shape_dom[1]),
                 "kernel_source_sha256": kernel_source_hash()}

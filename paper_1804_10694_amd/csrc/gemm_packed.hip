@@ -281,16 +281,19 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
 {
     if (CF::MODE == MODE_F32) {
         // element e of a lane's unit is k = 4*(2g + lane/32) + e for both
-        // operands, so MFMA e pairs equal k in A and B
+        // operands, so MFMA e pairs equal k in A and B.  (The elements are
+        // copied out before the bit cast: a bit cast applied to a vector
+        // element in place compiles to a read of element 0.)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
             for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
-                for (int j = 0; j < CF::TN; ++j)
+                for (int j = 0; j < CF::TN; ++j) {
+                    const uint32_t xa = o.a[0][i][0][e], xb = o.b[0][j][0][e];
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                        __builtin_bit_cast(float, o.a[0][i][0][e]), __builtin_bit_cast(float, o.b[0][j][0][e]),
-                        acc[i][j], 0, 0, 0);
+                        __builtin_bit_cast(float, xa), __builtin_bit_cast(float, xb), acc[i][j], 0, 0, 0);
+                }
     } else if (CF::MODE == MODE_FP8) {
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)

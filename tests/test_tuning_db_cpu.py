@@ -71,3 +71,15 @@ def test_autotune_rejects_bad_arguments(tg, tmp_path):
     assert tg.lib.tgemm_autotune(4, 4, 4, 7, 3, p) == -2
     assert tg.lib.tgemm_autotune(4, 4, 4, 0, 0, p) == -1
     assert tg.lib.tgemm_autotune(4, 4, 4, 0, 3, None) == -1
+
+
+def test_default_rule_packs_large_problems_only(tg):
+    # Large problems take the packed-operand kernels (the packing pass is O(MK + KN)
+    # against O(MNK)); small ones the direct kernels, which need no workspace.
+    tg.set_policy("default")
+    for dt in ("f32", "x3", "bf16", "fp8"):
+        big = tg.schedule_info(tg.select_schedule(8192, 8192, 8192, dt)[0])
+        assert big["vec"] == 0, (dt, big)
+        small = tg.schedule_info(tg.select_schedule(256, 256, 256, dt)[0])
+        assert small["vec"] in (1, 4), (dt, small)
+    assert tg.schedule_info(tg.select_schedule(8192, 8192, 8192, "f32")[0])["BM"] == 128
