@@ -150,12 +150,13 @@ def cmd_stats(args):
 
 
 def calibration(dispatches, counter):
-    """Counter value (KiB) of the closing device copy: the copy dispatches after the last gemm."""
+    """Counter value (KiB) of the closing 1 GiB device copy: the last dispatch of the run,
+    which must be a copy kernel after the last gemm (the smaller copies before it move
+    results to the host through staging buffers)."""
     last = max(i for i, d in enumerate(dispatches) if kind(d["name"]) in MAIN_KERNELS)
-    tail = [d for d in dispatches[last + 1:] if COPY_KERNEL in d["name"]]
-    if not tail:
-        raise ValueError("no calibration copy after the last gemm kernel")
-    return sum(d["counters"][counter] for d in tail), len(tail)
+    if last == len(dispatches) - 1 or COPY_KERNEL not in dispatches[-1]["name"]:
+        raise ValueError("the run does not end with the calibration copy")
+    return dispatches[-1]["counters"][counter], 1
 
 
 def cmd_traffic(args):

@@ -48,8 +48,8 @@ def test_traffic_groups_calls_and_applies_calibration(tmp_path):
     profsum.cmd_traffic(A)
     t = json.loads(table.read_text())
     rec = t["sched:0:a@256x256x256"]
-    # fetch: copy reads 2^20 / 2 + 5 KiB after the last gemm... the stray copy counts too
-    f_factor = 2 ** 30 / ((2 ** 20 / 2 + 5.0) * 1024)
+    # the last dispatch is the calibration copy; the smaller copy before it does not count
+    f_factor = 2 ** 30 / ((2 ** 20 / 2) * 1024)
     w_factor = 2 ** 30 / ((2 ** 20 / 4) * 1024)
     # timed calls (cold one dropped): 100 and 160 KiB fetched, 10 and 16 KiB written
     assert abs(rec["read_bytes"] - 130.0 * 1024 * f_factor) < 1e-6 * rec["read_bytes"]
