@@ -169,7 +169,7 @@ def extra_rows(tg, inputs):
     gbytes = float(sum(4.0 * (m * k + k * n_ + 2 * m * n_) for m, n_, k in dims))
     for dt in ("f32", "x3"):
         al, be = [1.0] * len(dims), [0.5] * len(dims)
-        threshold = tg.gemm_batched_autotune(As, Bs, Cs, al, be, dt, reps=5)   # tile shapes
+        shape = tg.gemm_batched_autotune(As, Bs, Cs, al, be, dt, reps=5)   # plan shape
         tg.gemm_batched(As, Bs, Cs, al, be, dt)          # plans
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
@@ -183,7 +183,7 @@ def extra_rows(tg, inputs):
             "tflops": round(gflops / (avg * 1e-3) / 1e12, 2),
             "hbm_gbs_compulsory": round(gbytes / (avg * 1e-3) / 1e9, 1),
             "floor_ms": round(floor_ms, 4), "frac_of_floor": round(floor_ms / avg, 4),
-            "tile128_threshold": threshold,
+            "tile128_threshold": shape["threshold"], "packed_operands": shape["packed"],
             "bound": "mfma" if gflops / (PEAK_TFLOPS[dt] * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
             else "hbm"}
         del graph

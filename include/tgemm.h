@@ -125,9 +125,13 @@ int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx
  * problem set (dimensions, leading dimensions, pointers, alpha, beta, dtype)
  * chooses a schedule per problem, builds the tile index space and uploads a
  * descriptor table to device memory owned by the library; later calls with
- * the same set launch one kernel.  The tile shape of a problem is 128 x 128
- * when both M and N reach a threshold, 64 x 64 otherwise: the threshold
- * tgemm_batched_autotune measured for sets of these dimensions, else 96.
+ * the same set launch one kernel (three for a packed plan: A packing, B
+ * packing, tiles).  The tile shape of a problem is 128 x 128 when both M and
+ * N reach a threshold, 64 x 64 otherwise; threshold and operand path are what
+ * tgemm_batched_autotune measured for sets of these dimensions, else 96 and
+ * direct.  A packed plan owns a workspace of about 4 bytes per element of
+ * every A and B (rows padded to the tile, K to a multiple of 32) until
+ * tgemm_shutdown.
  * If `stream` is capturing and the set has
  * no plan yet, the call returns TGEMM_CAPTURE_UNPLANNED: call once outside
  * capture first.  dtype: TGEMM_F32 or TGEMM_F32_BF16X3.
@@ -138,26 +142,48 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
                   float* const* C, const int64_t* ldc, int dtype, void* stream);
 
 /*
+ * tgemm_batched with the plan shape fixed by the caller instead of tuned or
+ * defaulted (project addition): 128 x 128 macro-tiles for problems whose M
+ * and N both reach `threshold` (>= 0; INT32_MAX: 64 x 64 everywhere), and
+ * packed (`packed` = 1) or direct (0) operands, as described for
+ * tgemm_batched_autotune below.  Plans are cached per shape.  Returns
+ * TGEMM_INVALID_VALUE for a negative threshold or a packed flag other than 0
+ * or 1, otherwise as tgemm_batched.
+ */
+int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
+                             const float* alpha, const void* const* A, const int64_t* lda,
+                             const void* const* B, const int64_t* ldb, const float* beta,
+                             float* const* C, const int64_t* ldc, int dtype, int threshold,
+                             int packed, void* stream);
+
+/*
  * Tile-shape autotuner of the grouped launch (project addition; the paper
  * chooses tile sizes by measurement, Section VI-A).  Same arguments as
- * tgemm_batched plus `reps`.  A problem gets 128 x 128 macro-tiles when both
- * its M and N reach a threshold T, 64 x 64 otherwise; the tuner times one
- * launch of the whole set for each T in {0, 64, 96, 160, 256, 512, never}
- * (thresholds that assign every problem the same tiles are timed once),
- * takes the median of `reps` timed launches after one warm-up, and keeps the
- * fastest T for problem sets of these dimensions (M, N, K, alpha == 0 and
- * load width per problem).  Later tgemm_batched calls on such sets use it;
- * cached plans of these dimensions are discarded, so a graph captured over
- * one must be captured again.  C is restored to its contents at entry
- * (the timed launches overwrite it; a device copy of C is allocated for
- * the call).  Synchronises `stream`.  Not allowed while `stream` captures.
- * Returns the threshold chosen (>= 0; INT32_MAX means 64 x 64 everywhere)
- * or -status.  reps in [1, 1000].
+ * tgemm_batched plus `reps` and two host output pointers.  A plan has two
+ * knobs: a threshold T (a problem gets 128 x 128 macro-tiles when both its M
+ * and N reach T, 64 x 64 otherwise; T in {0, 64, 96, 160, 256, 512, never})
+ * and the operand path: packed (a packing pre-pass copies every problem's A
+ * and B^T into a plan-owned workspace, K-contiguous and zero-padded, then the
+ * tiles stream K panels from it straight into LDS) or direct (tiles load A
+ * and B from the caller's matrices).  The tuner times one launch of the whole
+ * set per combination (combinations that assign every problem the same tiles
+ * are timed once), takes the median of `reps` timed launches after one
+ * warm-up, and keeps the fastest for problem sets of these dimensions (M, N,
+ * K, alpha == 0 and load width per problem).  Later tgemm_batched calls on
+ * such sets use it; cached plans of these dimensions are discarded, so a
+ * graph captured over one must be captured again.  C is restored to its
+ * contents at entry (the timed launches overwrite it; a device copy of C is
+ * allocated for the call).  Synchronises `stream`.  Returns
+ * TGEMM_CAPTURE_UNPLANNED while `stream` captures.  On success *threshold_out
+ * holds T (INT32_MAX: 64 x 64 everywhere) and *packed_out 1 (packed) or 0
+ * (direct).  reps in [1, 1000].  Without tuning, tgemm_batched uses T = 96,
+ * direct.
  */
 int tgemm_batched_autotune(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                            const float* alpha, const void* const* A, const int64_t* lda,
                            const void* const* B, const int64_t* ldb, const float* beta,
-                           float* const* C, const int64_t* ldc, int dtype, int reps, void* stream);
+                           float* const* C, const int64_t* ldc, int dtype, int reps, void* stream,
+                           int* threshold_out, int* packed_out);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* tgemm_status_string(int status);

@@ -1,0 +1,552 @@
+// Device code of the packed-operand gemm (all MFMA forms): the K-panel
+// pipeline from packed, K-contiguous operand buffers into LDS and the MFMA
+// register tiles, for one macro-tile.  Shared by the one-problem packed
+// kernels (gemm_packed.hip) and the grouped launch (batched.hip).
+//
+// Packing (Tiramisu paper, Section I, array packing after Goto and van de
+// Geijn): A (M x K) and B (K x N), row-major, are copied into buffers whose
+// rows are K-contiguous, in the element type the MFMA reads:
+//   Ap[m][k] = conv(A[m][k]),   Bp[n][k] = conv(B[k][n])   (B transposed)
+// where conv is the x3 split (two arrays, hi and lo) or a plain copy of the
+// values (f32) or codes (bf16, e4m3).  Rows are padded to whole macro-tiles
+// and K to whole panels, with zeros, so the main loop's loads carry no
+// predicates; full/partial tiles (Section V-C) differ only in the epilogue.
+//
+// Main loop: K panels of BK go from the packed buffers straight into LDS with
+// buffer_load ... lds (16 bytes per lane, no register staging); NS stages,
+// NS - 1 panels in flight, one barrier per panel.  LDS rows hold a panel's
+// 16-byte units of one packed row, XOR-swizzled so that the MFMA operand
+// reads of 16 consecutive rows hit distinct banks.
+//
+// Scaled forms: the running sum is kept divided by the current K block's
+// scale product and rescaled when the K block changes:
+// acc <- acc * (s_prev / s_cur) at each 128-wide K block, C = alpha * s_last * acc.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kargs.h"
+#include "tile_f32x3.h"
+
+namespace tg {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ packing
+// Element bytes of the source matrices: float for f32 and x3, codes for bf16
+// and e4m3.
+template <int MODE>
+constexpr int src_bytes() { return MODE == MODE_FP8 ? 1 : MODE == MODE_BF16 ? 2 : 4; }
+
+// Host side: whether rows of X (element size es bytes, row stride ld
+// elements) allow the vector loads of pack_row_group (8 elements, 16-byte
+// loads; 8 bytes for 1-byte codes) and of pack_col_block (4 elements).
+inline int pack_rows_vec(const void* X, int64_t ld, int es)
+{
+    const int64_t need = es == 1 ? 8 : 16;
+    return (reinterpret_cast<uintptr_t>(X) % need == 0) && ((ld * es) % need == 0);
+}
+inline int pack_cols_vec(const void* X, int64_t ld, int es)
+{
+    const int64_t need = 4 * es;
+    return (reinterpret_cast<uintptr_t>(X) % need == 0) && ((ld * es) % need == 0);
+}
+
+// A-side, one group of 8 consecutive k of row r: X (R x K, row stride ldx)
+// -> P (row stride Kp); zero beyond R and K.  x3: X is float, P / Plo receive
+// the bf16 hi and lo parts.  f32: floats, copied.  bf16 / e4m3: X holds codes,
+// copied.  vec: X and its row stride allow one 8-element vector load per
+// group (16-byte aligned rows; 8-byte for e4m3), used for groups wholly
+// inside the matrix.
+template <int MODE>
+__device__ __forceinline__ void pack_row_group(const void* X, int64_t ldx, int R, int K, void* P,
+                                               void* Plo, int Kp, int r, int k0, bool vec)
+{
+    constexpr int ES = src_bytes<MODE>();
+    const bool whole = vec && r < R && k0 + 8 <= K;
+    const char* src = static_cast<const char*>(X) + ((int64_t)r * ldx + k0) * ES;
+    const int64_t o = (int64_t)r * Kp + k0;
+    if (MODE == MODE_F32 || MODE == MODE_X3) {
+        f32x4 v0, v1;
+        if (whole) {
+            v0 = *reinterpret_cast<const f32x4*>(src);
+            v1 = *reinterpret_cast<const f32x4*>(src + 16);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = (r < R && k0 + e < K) ? reinterpret_cast<const float*>(src)[e] : 0.f;
+                if (e < 4) v0[e] = v;
+                else v1[e - 4] = v;
+            }
+        }
+        if (MODE == MODE_F32) {
+            float* dst = static_cast<float*>(P) + o;
+            *reinterpret_cast<f32x4*>(dst) = v0;
+            *reinterpret_cast<f32x4*>(dst + 4) = v1;
+        } else {
+            bf16x8 h, l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                __bf16 hh, ll;
+                split_bf16(e < 4 ? v0[e] : v1[e - 4], hh, ll);
+                h[e] = hh;
+                l[e] = ll;
+            }
+            *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(P) + o) = h;
+            *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(Plo) + o) = l;
+        }
+    } else if (MODE == MODE_BF16) {
+        u32x4 w;
+        if (whole) {
+            w = *reinterpret_cast<const u32x4*>(src);
+        } else {
+            uint32_t c[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                c[e] = (r < R && k0 + e < K) ? reinterpret_cast<const uint16_t*>(src)[e] : 0u;
+            w = u32x4{c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16)};
+        }
+        *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(P) + o) = w;
+    } else {
+        uint2 w;
+        if (whole) {
+            w = *reinterpret_cast<const uint2*>(src);
+        } else {
+            uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t v = (r < R && k0 + e < K) ? reinterpret_cast<const uint8_t*>(src)[e] : 0u;
+                if (e < 4) w0 |= v << (8 * e);
+                else w1 |= v << (8 * (e - 4));
+            }
+            w = make_uint2(w0, w1);
+        }
+        *reinterpret_cast<uint2*>(static_cast<uint8_t*>(P) + o) = w;
+    }
+}
+
+// B-side, one 64 x 64 block (n0, k0): X (K x N, row stride ldx) -> P (row
+// stride Kp) = X^T, through the LDS `tile` (x3 and f32: float values; codes
+// widened to 32 bits).  Reads: 16 lanes cover 64 consecutive n of one k row,
+// four elements each (one vector load when vec and the four lie inside the
+// matrix); writes: each lane stores 16 consecutive k of one packed row with
+// 16-byte stores.  Zero beyond K and N; nothing written at or beyond Np, and
+// Kp must be a multiple of 16.  256 threads; ends with a barrier, so `tile`
+// can be reused at once.  vec: rows of X are aligned for 4-element vector
+// loads.
+template <int MODE>
+__device__ __forceinline__ void pack_col_block(const void* X, int64_t ldx, int K, int N, void* P,
+                                               void* Plo, int Np, int Kp, int n0, int k0,
+                                               float (&tile)[64][65], bool vec)
+{
+    constexpr int ES = src_bytes<MODE>();
+    const int t = threadIdx.x;
+    {
+        const int n4 = t & 15, kr = t >> 4;  // 16 x 16 threads; 4 passes over 64 rows
+        const int n = n0 + 4 * n4;
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) {
+            const int kk = kr + 16 * pass, k = k0 + kk;
+            const char* src = static_cast<const char*>(X) + ((int64_t)k * ldx + n) * ES;
+            float v[4];
+            if (vec && k < K && n + 4 <= N) {
+                if (ES == 4) {
+                    const f32x4 x = *reinterpret_cast<const f32x4*>(src);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) v[c] = x[c];
+                } else if (ES == 2) {
+                    const uint2 x = *reinterpret_cast<const uint2*>(src);
+                    v[0] = __uint_as_float(x.x & 0xffffu);
+                    v[1] = __uint_as_float(x.x >> 16);
+                    v[2] = __uint_as_float(x.y & 0xffffu);
+                    v[3] = __uint_as_float(x.y >> 16);
+                } else {
+                    const uint32_t x = *reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) v[c] = __uint_as_float((x >> (8 * c)) & 0xffu);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    v[c] = 0.f;
+                    if (k < K && n + c < N) {
+                        if (ES == 4) v[c] = reinterpret_cast<const float*>(src)[c];
+                        else if (ES == 2) v[c] = __uint_as_float(reinterpret_cast<const uint16_t*>(src)[c]);
+                        else v[c] = __uint_as_float(reinterpret_cast<const uint8_t*>(src)[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tile[kk][4 * n4 + c] = v[c];
+        }
+    }
+    __syncthreads();
+    {
+        const int nn = t >> 2, kq = t & 3;  // packed row n0 + nn, k0 + 16 kq .. + 15
+        const int n = n0 + nn, k = k0 + 16 * kq;
+        if (n < Np && k < Kp) {
+            const int64_t o = (int64_t)n * Kp + k;
+            float v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = tile[16 * kq + j][nn];
+            if (MODE == MODE_F32) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<f32x4*>(static_cast<float*>(P) + o + 4 * q) =
+                        f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+            } else if (MODE == MODE_X3) {
+                bf16x8 h[2], l[2];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    __bf16 hh, ll;
+                    split_bf16(v[j], hh, ll);
+                    h[j / 8][j % 8] = hh;
+                    l[j / 8][j % 8] = ll;
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(P) + o + 8 * q) = h[q];
+                    *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(Plo) + o + 8 * q) = l[q];
+                }
+            } else if (MODE == MODE_BF16) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        w[e] = __float_as_uint(v[8 * q + 2 * e]) | (__float_as_uint(v[8 * q + 2 * e + 1]) << 16);
+                    *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(P) + o + 8 * q) = u32x4{w[0], w[1], w[2], w[3]};
+                }
+            } else {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    w[e] = __float_as_uint(v[4 * e]) | (__float_as_uint(v[4 * e + 1]) << 8) |
+                           (__float_as_uint(v[4 * e + 2]) << 16) | (__float_as_uint(v[4 * e + 3]) << 24);
+                *reinterpret_cast<u32x4*>(static_cast<uint8_t*>(P) + o) = u32x4{w[0], w[1], w[2], w[3]};
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ main loop
+template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_>
+struct PCfg {
+    static constexpr int MODE = MODE_, BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
+    static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
+    // waves per SIMD the register allocation must allow: two workgroups per CU
+    // when one workgroup's LDS fits in half of the 160 KB
+    static constexpr int ES = (MODE == MODE_FP8) ? 1 : (MODE == MODE_F32) ? 4 : 2;  // bytes
+    static constexpr int WAVES_PER_EU =
+        (NS_ * (MODE_ == MODE_X3 ? 2 : 1) * (BM_ + BN_) * BK_ * ES <= 80 * 1024 && WGM_ * WGN_ == 4) ? 2 : 1;
+    static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
+    static constexpr int KU = 16 / ES;                   // k per 16-byte unit
+    static constexpr int UK = BK / KU;                   // units per packed row per panel
+    // k per MFMA group: 32x32x64 e4m3, 32x32x16 bf16; f32 runs the four
+    // 32x32x2 MFMAs of one unit per lane as a group of 8 k
+    static constexpr int MK = (MODE == MODE_FP8) ? 64 : (MODE == MODE_F32) ? 8 : 16;
+    static constexpr int UPL = MK / KU / 2;              // units per lane per group
+    static constexpr int NG = BK / MK;
+    static constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 32, TN = WTN / 32;
+    static constexpr int NARR = (MODE == MODE_X3) ? 2 : 1;
+    static constexpr int LDS_A = BM * UK * 16, LDS_B = BN * UK * 16;
+    static constexpr int LDS_STAGE = NARR * (LDS_A + LDS_B);
+    static constexpr int LDS_BYTES = NS * LDS_STAGE;
+    // direct-to-LDS instructions (64 units each) per wave per array per panel
+    static constexpr int A_INSTR = BM * UK / 64 / NW, B_INSTR = BN * UK / 64 / NW;
+    static constexpr int LOADS_PER_STAGE = NARR * (A_INSTR + B_INSTR);
+    static_assert(NS >= 2 && (NS - 2) * LOADS_PER_STAGE <= 63, "vmcnt holds at most 63");
+    // a panel never straddles a 128-wide K scale block
+    static_assert(BK % MK == 0 && 128 % BK == 0, "panels tile K");
+    static_assert((BM * UK) % (64 * NW) == 0 && (BN * UK) % (64 * NW) == 0, "loads divide among waves");
+    static_assert(UK <= 16 && 16 % UK == 0, "swizzle");
+    static_assert(WTM % 32 == 0 && WTN % 32 == 0, "whole blocks");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS");
+};
+
+// Physical unit of (row, logical unit u): rows of UK units, u XORed with bits
+// of the row so that 16 consecutive rows at fixed u fall on 16 distinct
+// 16-byte bank groups.
+template <int UK>
+__device__ __forceinline__ int pk_slot(int row, int u)
+{
+    return row * UK + (u ^ ((row / (16 / UK)) & (UK - 1)));
+}
+
+// Issue the direct-to-LDS loads of one panel for one packed array.  Wave
+// instruction ig moves 64 consecutive LDS units: rows ig*(64/UK) .. of the
+// tile, all UK units of each.  Lane l takes LDS unit ig*64 + l, i.e. row
+// ig*(64/UK) + l/UK, physical column l%UK, which holds logical unit
+// (l%UK) ^ f(row).  For the swizzle f(row) = (row / (16/UK)) & (UK-1) this is
+// (l%UK) ^ (l/16) ^ ((4*ig) & (UK-1)): one per-lane byte offset (lane_off)
+// XORed with a uniform constant per instruction.  The row part of the
+// address is the uniform soffset, so each load costs one VGPR at most.
+template <int UK, int NI>
+__device__ __forceinline__ void load_panel(__amdgpu_buffer_rsrc_t rsrc, int lane_off, int row_bytes,
+                                           int k_byte0, char* lds, int wave)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int ig = wave * NI + i;
+        const int voff = lane_off ^ (((4 * ig) & (UK - 1)) * 16);
+        const int soff = ig * (64 / UK) * row_bytes + k_byte0;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rsrc, (__attribute__((address_space(3))) void*)(lds + ig * 64 * 16), 16, voff, soff, 0, 0);
+    }
+}
+
+// Buffer resource over `bytes` bytes from `base` (raw, untyped 32-bit format);
+// reads beyond `bytes` return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const char* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, bytes, 0x00020000);
+}
+
+// s_waitcnt vmcnt(N) with expcnt and lgkmcnt left unconstrained (gfx9 encoding:
+// vmcnt[3:0] in bits 3:0, vmcnt[5:4] in bits 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+struct PackedArgs {
+    const char* A;    // packed A (hi), Rp_a x Kp
+    const char* Alo;  // x3: packed A lo
+    const char* B;    // packed B^T (hi), Rp_b x Kp
+    const char* Blo;
+    float* C;
+    const float* sA;
+    const float* sB;
+    int64_t ldc, lds_a, lds_b;
+    int M, N, K, Kp;
+    float alpha, beta;
+    int tiles_m, tiles_n, group_m, xcd_remap;
+};
+
+// Operands of one MFMA group (MK consecutive k) for all of a wave's blocks.
+template <class CF>
+struct PkOps {
+    static constexpr int AV = (CF::MODE == MODE_FP8) ? 2 : 1;  // 16-byte units per operand
+    static constexpr int NA = (CF::MODE == MODE_X3) ? 2 : 1;   // hi (+ lo)
+    u32x4 a[NA][CF::TM][AV];
+    u32x4 b[NA][CF::TN][AV];
+};
+
+template <class CF>
+__device__ __forceinline__ void pk_load(const char* stage, PkOps<CF>& o, int g, int wm0, int wn0,
+                                        int lane)
+{
+    constexpr int UK = CF::UK, UPL = CF::UPL;
+    const int h = lane >> 5, l32 = lane & 31;
+#pragma unroll
+    for (int v = 0; v < PkOps<CF>::AV; ++v) {
+        const int u = (2 * g + h) * UPL + v;
+#pragma unroll
+        for (int x = 0; x < PkOps<CF>::NA; ++x) {
+            const char* la = stage + x * CF::LDS_A;
+            const char* lb = stage + CF::NARR * CF::LDS_A + x * CF::LDS_B;
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+                o.a[x][i][v] = *reinterpret_cast<const u32x4*>(la + pk_slot<UK>(wm0 + 32 * i + l32, u) * 16);
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j)
+                o.b[x][j][v] = *reinterpret_cast<const u32x4*>(lb + pk_slot<UK>(wn0 + 32 * j + l32, u) * 16);
+        }
+    }
+}
+
+template <class CF>
+__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN])
+{
+    if (CF::MODE == MODE_F32) {
+        // element e of a lane's unit is k = 4*(2g + lane/32) + e for both
+        // operands, so MFMA e pairs equal k in A and B.  (The elements are
+        // copied out before the bit cast: a bit cast applied to a vector
+        // element in place compiles to a read of element 0.)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j) {
+                    const uint32_t xa = o.a[0][i][0][e], xb = o.b[0][j][0][e];
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                        __builtin_bit_cast(float, xa), __builtin_bit_cast(float, xb), acc[i][j], 0, 0, 0);
+                }
+    } else if (CF::MODE == MODE_FP8) {
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const u32x4 a0 = o.a[0][i][0], a1 = o.a[0][i][PkOps<CF>::AV - 1];
+                const u32x4 b0 = o.b[0][j][0], b1 = o.b[0][j][PkOps<CF>::AV - 1];
+                const i32x8 x = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                                 (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                const i32x8 y = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                                 (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+                // format codes 0/0: both operands OCP e4m3; no block scaling
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[i][j], 0, 0, 0, 0, 0, 0);
+            }
+    } else {
+        if (CF::MODE == MODE_X3) {
+            // small terms first: lo*hi, hi*lo, then hi*hi
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, o.a[PkOps<CF>::NA - 1][i][0]),
+                        __builtin_bit_cast(bf16x8, o.b[0][j][0]), acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, o.a[0][i][0]),
+                        __builtin_bit_cast(bf16x8, o.b[PkOps<CF>::NA - 1][j][0]), acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, o.a[0][i][0]), __builtin_bit_cast(bf16x8, o.b[0][j][0]),
+                    acc[i][j], 0, 0, 0);
+    }
+}
+
+// MFMAs over one LDS stage.  Operand registers are double-buffered: the reads
+// of group g + 1 are issued before the MFMAs of group g, and the scheduler is
+// asked to interleave them, so LDS latency hides behind the matrix unit.
+template <class CF>
+__device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
+                                       int wn0, int lane)
+{
+    constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
+    constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
+    PkOps<CF> ops[2];
+    pk_load<CF>(stage, ops[0], 0, wm0, wn0, lane);
+#pragma unroll
+    for (int g = 0; g < CF::NG; ++g) {
+        if (g + 1 < CF::NG) pk_load<CF>(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
+        pk_compute<CF>(ops[g & 1], acc);
+        if (g + 1 < CF::NG) {
+            // one LDS read between consecutive MFMAs while both last
+#pragma unroll
+            for (int k = 0; k < (NREAD < NMFMA ? NREAD : NMFMA); ++k) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            }
+        }
+    }
+}
+
+// Scale product of block (row0, col0) for K scale block kb.
+// (row0, col0 and kb are wave-uniform, so the two loads are scalar loads and do
+// not count against vmcnt, which tracks the panel pipeline.)
+__device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int col0, int kb)
+{
+    if (row0 >= a.M || col0 >= a.N) return 1.f;  // a block of padding: never stored
+    const int64_t ia = __builtin_amdgcn_readfirstlane((int)((row0 / 128) * a.lds_a + kb));
+    const int64_t ib = __builtin_amdgcn_readfirstlane((int)(kb * a.lds_b + col0 / 128));
+    return a.sA[ia] * a.sB[ib];
+}
+
+// One BM x BN macro-tile at (m0, n0) of the packed problem `a`; `lds` holds
+// CF::LDS_BYTES.  The packed rows of A and B^T must extend to m0 + BM and
+// n0 + BN, and K to a multiple of BK, with zeros beyond K.
+template <class CF>
+__device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds)
+{
+    const int t = threadIdx.x, lane = t & 63;
+    // the wave index is uniform; readfirstlane lets the compiler keep it (and the
+    // load offsets and LDS bases derived from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm0 = (wave / CF::WGN) * CF::WTM, wn0 = (wave % CF::WGN) * CF::WTN;
+    const int row_bytes = a.Kp * CF::ES;
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(a.B + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
+    __amdgpu_buffer_rsrc_t rAl = rA, rBl = rB;
+    if (CF::MODE == MODE_X3) {
+        rAl = make_rsrc(a.Alo + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
+        rBl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
+    }
+    const int lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
+    const bool scaled = (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA;
+
+    f32x16 acc[CF::TM][CF::TN];
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int npanel = (a.K + CF::BK - 1) / CF::BK;
+    auto issue = [&](int panel, char* stage) {
+        const int kb = panel * CF::BK * CF::ES;
+        load_panel<CF::UK, CF::A_INSTR>(rA, lane_off, row_bytes, kb, stage, wave);
+        if (CF::MODE == MODE_X3)
+            load_panel<CF::UK, CF::A_INSTR>(rAl, lane_off, row_bytes, kb, stage + CF::LDS_A, wave);
+        char* sb = stage + CF::NARR * CF::LDS_A;
+        load_panel<CF::UK, CF::B_INSTR>(rB, lane_off, row_bytes, kb, sb, wave);
+        if (CF::MODE == MODE_X3)
+            load_panel<CF::UK, CF::B_INSTR>(rBl, lane_off, row_bytes, kb, sb + CF::LDS_B, wave);
+    };
+
+    // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
+    constexpr int NS = CF::NS;
+    for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
+    int kb_cur = 0;
+    for (int s = 0; s < npanel; ++s) {
+        // this wave's loads of panel s have landed once at most the loads of the
+        // panels issued after it remain; then the barrier covers every wave's loads
+        // and frees the stage that panel s - 1 occupied
+        if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * CF::LOADS_PER_STAGE>();
+        else wait_vmcnt<0>();
+        __syncthreads();
+        if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
+        if (scaled) {
+            const int kb = (s * CF::BK) / 128;
+            if (s > 0 && kb != kb_cur) {
+                // new K scale block: keep acc divided by the current scale product
+#pragma unroll
+                for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < CF::TN; ++j) {
+                        const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+                        const float ratio = block_scale(a, r0, c0, kb_cur) / block_scale(a, r0, c0, kb);
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                    }
+                kb_cur = kb;
+            }
+        }
+        pk_mma<CF>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+    }
+
+    const int h = lane >> 5, l32 = lane & 31;
+    const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
+    const bool read_c = (a.beta != 0.f);
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::TN; ++j) {
+            const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+            const float sc = a.alpha * (scaled ? block_scale(a, r0, c0, kb_cur) : 1.f);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int col = c0 + l32;
+                if (!full && (row >= a.M || col >= a.N)) continue;
+                float* p = a.C + (int64_t)row * a.ldc + col;
+                float v = sc * acc[i][j][r];
+                if (read_c) v = fmaf(a.beta, *p, v);
+                *p = v;
+            }
+        }
+}
+
+}  // namespace tg

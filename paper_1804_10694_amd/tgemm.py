@@ -38,8 +38,10 @@ lib.tgemm_scaled.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _p, _i64, _p,
 lib.tgemm_quantize_tiles.argtypes = [_i64, _i64, _p, _i64, _p, _i64, _p, _i32, _p]
 lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32, _pp,
                               _pi64, _i32, _p]
+lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
+                                         _pf32, _pp, _pi64, _i32, _i32, _i32, _p]
 lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
-                                       _pp, _pi64, _i32, _i32, _p]
+                                       _pp, _pi64, _i32, _i32, _p, _pi32, _pi32]
 lib.tgemm_status_string.argtypes = [_i32]
 lib.tgemm_status_string.restype = ctypes.c_char_p
 lib.tgemm_set_policy.argtypes = [ctypes.c_char_p]
@@ -189,10 +191,16 @@ def _arr(ctype, values):
     return (ctype * len(values))(*values)
 
 
-def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None):
-    """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p."""
-    rc = lib.tgemm_batched(*_batched_args(As, Bs, Cs, alphas, betas, dtype), _stream_handle(stream))
-    _check(rc, "tgemm_batched")
+def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None, shape=None):
+    """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p.
+    shape: None (tuned or default plan shape) or {"threshold": T, "packed": bool}
+    (tgemm_batched_with_shape)."""
+    args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
+    if shape is None:
+        _check(lib.tgemm_batched(*args, _stream_handle(stream)), "tgemm_batched")
+    else:
+        _check(lib.tgemm_batched_with_shape(*args, int(shape["threshold"]), 1 if shape["packed"] else 0,
+                                            _stream_handle(stream)), "tgemm_batched_with_shape")
 
 
 def _batched_args(As, Bs, Cs, alphas, betas, dtype):
@@ -214,13 +222,13 @@ def _batched_args(As, Bs, Cs, alphas, betas, dtype):
 
 
 def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream=None):
-    """Tile-shape tuning of a grouped set (tgemm_batched_autotune); returns the
-    128x128-tile threshold chosen (2**31 - 1: 64x64 tiles everywhere)."""
+    """Plan-shape tuning of a grouped set (tgemm_batched_autotune); returns
+    {"threshold": T, "packed": bool} (T = 2**31 - 1: 64x64 tiles everywhere)."""
     args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
-    rc = lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream))
-    if rc < 0:
-        raise TgemmError(-rc, "tgemm_batched_autotune")
-    return rc
+    thr, packed = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream), ctypes.byref(thr),
+                                      ctypes.byref(packed)), "tgemm_batched_autotune")
+    return {"threshold": thr.value, "packed": bool(packed.value)}
 
 
 def set_policy(policy):

@@ -34,17 +34,26 @@ def _problem_set(dims, seed_base, integer=False):
     return host
 
 
-def _run_batched(tg, host, alphas, betas, dtype):
+NEVER = 2**31 - 1
+# plan shapes: the default (tuned or built-in), and forced packed / direct operands with
+# mixed, all-128 and all-64 macro-tiles
+SHAPES = [None] + [{"threshold": t, "packed": pk} for pk in (True, False) for t in (96, 0, NEVER)]
+SHAPE_IDS = ["default"] + [f"{'packed' if pk else 'direct'}-{t if t != NEVER else 'all64'}"
+                           for pk in (True, False) for t in (96, 0, NEVER)]
+
+
+def _run_batched(tg, host, alphas, betas, dtype, shape=None):
     As = [h[0].to(DEV) for h in host]
     Bs = [h[1].to(DEV) for h in host]
     Cs = [h[2].clone().to(DEV) for h in host]
-    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape=shape)
     torch.cuda.synchronize()
     return [c.cpu() for c in Cs]
 
 
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_small_set_bit_exact_on_integers(tg, dtype):
+def test_small_set_bit_exact_on_integers(tg, dtype, shape):
     rng = np.random.default_rng(51)
     dims = rng.integers(1, 300, size=(60, 3))
     dims[3] = (0, 5, 7)          # empty problems launch nothing
@@ -55,13 +64,15 @@ def test_small_set_bit_exact_on_integers(tg, dtype):
     host = _problem_set(dims, 5000, integer=True)
     alphas = [1.5 if p % 2 else 1.0 for p in range(len(dims))]
     betas = [0.5 if p % 3 else 0.0 for p in range(len(dims))]
-    got = _run_batched(tg, host, alphas, betas, dtype)
+    print(f"{dtype} shape {shape}", flush=True)
+    got = _run_batched(tg, host, alphas, betas, dtype, shape)
     for p, (h, g) in enumerate(zip(host, got)):
         ref = oracle.gemm(h[0], h[1], h[2], alphas[p], betas[p])
         np.testing.assert_array_equal(g.numpy().astype(np.float64), ref, err_msg=f"problem {p} {dims[p]}")
 
 
-def test_alpha_zero_and_padded_strides(tg):
+@pytest.mark.parametrize("packed", [True, False])
+def test_alpha_zero_and_padded_strides(tg, packed):
     # alpha == 0 must not read A (NaN there), and row strides wider than the matrices
     # (unaligned and aligned) take the 4-byte and 16-byte load configurations.
     dims = [(40, 50, 30), (200, 160, 120), (129, 257, 65), (96, 96, 96)]
@@ -79,7 +90,7 @@ def test_alpha_zero_and_padded_strides(tg):
         views.append(Cd)
     As[0] = torch.full_like(As[0], float("nan"))
     alphas, betas = [0.0, 1.0, 1.0, 2.0], [0.5, 0.5, 0.0, 1.0]
-    tg.gemm_batched(As, Bs, Cs, alphas, betas, "f32")
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, "f32", shape={"threshold": 96, "packed": packed})
     torch.cuda.synchronize()
     np.testing.assert_array_equal(Cs[0].cpu().numpy(), (0.5 * host[0][2]).numpy())
     for p in range(1, 4):
@@ -88,14 +99,15 @@ def test_alpha_zero_and_padded_strides(tg):
         assert torch.isnan(views[p][:, host[p][2].shape[1]:]).all()    # canaries intact
 
 
+@pytest.mark.parametrize("shape", [None, {"threshold": 96, "packed": False}], ids=["default", "direct"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_grouped_config_512_problems(tg, dtype):
+def test_grouped_config_512_problems(tg, dtype, shape):
     # 512 problems, M, N, K log-uniform in [16, 2048] (seed 4), matrices from seeds
     # 4000 + p, alpha = 1, beta = 0.5.
     dims = inputs.grouped_dims()
     host = _problem_set(dims, 4000)
     alphas, betas = [1.0] * len(dims), [0.5] * len(dims)
-    got = _run_batched(tg, host, alphas, betas, dtype)
+    got = _run_batched(tg, host, alphas, betas, dtype, shape)
     worst = 0.0
     for p, (h, g) in enumerate(zip(host, got)):
         ref = oracle.gemm(h[0], h[1], h[2], 1.0, 0.5)
@@ -104,7 +116,8 @@ def test_grouped_config_512_problems(tg, dtype):
     assert worst <= 1e-5
 
 
-def test_graph_capture_replays_match_eager(tg):
+@pytest.mark.parametrize("packed", [True, False])
+def test_graph_capture_replays_match_eager(tg, packed):
     rng = np.random.default_rng(52)
     dims = rng.integers(16, 400, size=(40, 3))
     host = _problem_set(dims, 5200)
@@ -113,16 +126,17 @@ def test_graph_capture_replays_match_eager(tg):
     Bs = [h[1].to(DEV) for h in host]
     Cg = [h[2].clone().to(DEV) for h in host]        # graph-updated
     Ce = [h[2].clone().to(DEV) for h in host]        # eager-updated
+    shape = {"threshold": 96, "packed": packed}
     # plan exists before capture (first call plans; it also advances Cg once)
-    tg.gemm_batched(As, Bs, Cg, alphas, betas, "x3")
-    tg.gemm_batched(As, Bs, Ce, alphas, betas, "x3")
+    tg.gemm_batched(As, Bs, Cg, alphas, betas, "x3", shape=shape)
+    tg.gemm_batched(As, Bs, Ce, alphas, betas, "x3", shape=shape)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        tg.gemm_batched(As, Bs, Cg, alphas, betas, "x3")
+        tg.gemm_batched(As, Bs, Cg, alphas, betas, "x3", shape=shape)
     for r in range(3):
         graph.replay()
-        tg.gemm_batched(As, Bs, Ce, alphas, betas, "x3")
+        tg.gemm_batched(As, Bs, Ce, alphas, betas, "x3", shape=shape)
         torch.cuda.synchronize()
         for p in range(40):
             assert torch.equal(Cg[p], Ce[p]), f"replay {r} problem {p}"
@@ -179,7 +193,7 @@ def test_autotune_restores_c_and_tuned_plan_is_exact(tg, dtype):
     t = tg.gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype, reps=2)
     torch.cuda.synchronize()
     print(f"{dtype}: tuned threshold {t}", flush=True)
-    assert t in (0, 64, 96, 160, 256, 512, 2**31 - 1)
+    assert t["threshold"] in (0, 64, 96, 160, 256, 512, 2**31 - 1) and t["packed"] in (True, False)
     for p, (b, c) in enumerate(zip(before, Cs)):
         assert torch.equal(b, c), f"C of problem {p} not restored"
     tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
@@ -190,7 +204,9 @@ def test_autotune_restores_c_and_tuned_plan_is_exact(tg, dtype):
                                       err_msg=f"problem {p} {dims[p]}")
 
 
-def test_autotune_rejects_bad_reps(tg):
+def test_autotune_and_forced_shape_reject_bad_arguments(tg):
     A = torch.ones(8, 8, device=DEV)
     with pytest.raises(tg.TgemmError):
         tg.gemm_batched_autotune([A], [A], [A.clone()], [1.0], [0.0], "f32", reps=0)
+    with pytest.raises(tg.TgemmError):
+        tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "packed": True})
