@@ -38,6 +38,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 KERNEL_SOURCES = ["paper_1804_10694_amd/csrc/tile_f32x3.h", "paper_1804_10694_amd/csrc/gemm_tile.hip",
+                  "paper_1804_10694_amd/csrc/tile_packed.h",
                   "paper_1804_10694_amd/csrc/gemm_packed.hip", "paper_1804_10694_amd/csrc/kargs.h"]
 TRAFFIC_FILE = "profiles/traffic.json"
 
@@ -183,7 +184,7 @@ def extra_rows(tg, inputs):
             "tflops": round(gflops / (avg * 1e-3) / 1e12, 2),
             "hbm_gbs_compulsory": round(gbytes / (avg * 1e-3) / 1e9, 1),
             "floor_ms": round(floor_ms, 4), "frac_of_floor": round(floor_ms / avg, 4),
-            "tile128_threshold": shape["threshold"], "packed_operands": shape["packed"],
+            "tile128_threshold": shape["threshold"], "packed_256_threshold": shape["large"],
             "bound": "mfma" if gflops / (PEAK_TFLOPS[dt] * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
             else "hbm"}
         del graph

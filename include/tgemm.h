@@ -125,13 +125,12 @@ int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx
  * problem set (dimensions, leading dimensions, pointers, alpha, beta, dtype)
  * chooses a schedule per problem, builds the tile index space and uploads a
  * descriptor table to device memory owned by the library; later calls with
- * the same set launch one kernel (three for a packed plan: A packing, B
- * packing, tiles).  The tile shape of a problem is 128 x 128 when both M and
- * N reach a threshold, 64 x 64 otherwise; threshold and operand path are what
- * tgemm_batched_autotune measured for sets of these dimensions, else 96 and
- * direct.  A packed plan owns a workspace of about 4 bytes per element of
- * every A and B (rows padded to the tile, K to a multiple of 32) until
- * tgemm_shutdown.
+ * the same set launch at most three kernels (packing pass, packed-class
+ * tiles, direct-class tiles; see tgemm_batched_with_shape for the two
+ * classes).  The plan shape is what tgemm_batched_autotune measured for sets
+ * of these dimensions, else threshold 96 and no packed class.  A plan with packed
+ * problems owns a workspace of 4 bytes per element of their A and B (rows
+ * padded to 256, K to a multiple of 32) until tgemm_shutdown.
  * If `stream` is capturing and the set has
  * no plan yet, the call returns TGEMM_CAPTURE_UNPLANNED: call once outside
  * capture first.  dtype: TGEMM_F32 or TGEMM_F32_BF16X3.
@@ -143,30 +142,29 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
 
 /*
  * tgemm_batched with the plan shape fixed by the caller instead of tuned or
- * defaulted (project addition): 128 x 128 macro-tiles for problems whose M
- * and N both reach `threshold` (>= 0; INT32_MAX: 64 x 64 everywhere), and
- * packed (`packed` = 1) or direct (0) operands, as described for
- * tgemm_batched_autotune below.  Plans are cached per shape.  Returns
- * TGEMM_INVALID_VALUE for a negative threshold or a packed flag other than 0
- * or 1, otherwise as tgemm_batched.
+ * defaulted (project addition).  Problems whose M and N both reach `large`
+ * (>= 0; INT32_MAX: none) take the packed path: a packing pass copies their A
+ * and B^T into a plan-owned workspace (K-contiguous, zero-padded; array
+ * packing, Section I) and 256 x 256 macro-tiles stream K panels from it into
+ * LDS.  The other problems take the direct path: 128 x 128 macro-tiles when M
+ * and N both reach `threshold` (>= 0; INT32_MAX: 64 x 64 everywhere), 64 x 64
+ * otherwise, loading A and B from the caller's matrices.  Plans are cached
+ * per shape.  Returns TGEMM_INVALID_VALUE for a negative threshold, otherwise
+ * as tgemm_batched.
  */
 int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                              const float* alpha, const void* const* A, const int64_t* lda,
                              const void* const* B, const int64_t* ldb, const float* beta,
                              float* const* C, const int64_t* ldc, int dtype, int threshold,
-                             int packed, void* stream);
+                             int large, void* stream);
 
 /*
- * Tile-shape autotuner of the grouped launch (project addition; the paper
+ * Plan-shape autotuner of the grouped launch (project addition; the paper
  * chooses tile sizes by measurement, Section VI-A).  Same arguments as
- * tgemm_batched plus `reps` and two host output pointers.  A plan has two
- * knobs: a threshold T (a problem gets 128 x 128 macro-tiles when both its M
- * and N reach T, 64 x 64 otherwise; T in {0, 64, 96, 160, 256, 512, never})
- * and the operand path: packed (a packing pre-pass copies every problem's A
- * and B^T into a plan-owned workspace, K-contiguous and zero-padded, then the
- * tiles stream K panels from it straight into LDS) or direct (tiles load A
- * and B from the caller's matrices).  The tuner times one launch of the whole
- * set per combination (combinations that assign every problem the same tiles
+ * tgemm_batched plus `reps` and two host output pointers.  It times one
+ * launch of the whole set for every shape (threshold in {0, 64, 96, 160, 256,
+ * 512, never} x large in {256, 512, 1024, never}, as in
+ * tgemm_batched_with_shape; shapes that give every problem the same tiles
  * are timed once), takes the median of `reps` timed launches after one
  * warm-up, and keeps the fastest for problem sets of these dimensions (M, N,
  * K, alpha == 0 and load width per problem).  Later tgemm_batched calls on
@@ -174,16 +172,16 @@ int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, 
  * graph captured over one must be captured again.  C is restored to its
  * contents at entry (the timed launches overwrite it; a device copy of C is
  * allocated for the call).  Synchronises `stream`.  Returns
- * TGEMM_CAPTURE_UNPLANNED while `stream` captures.  On success *threshold_out
- * holds T (INT32_MAX: 64 x 64 everywhere) and *packed_out 1 (packed) or 0
- * (direct).  reps in [1, 1000].  Without tuning, tgemm_batched uses T = 96,
- * direct.
+ * TGEMM_CAPTURE_UNPLANNED while `stream` captures.  On success
+ * *threshold_out and *large_out hold the shape chosen (INT32_MAX: never).
+ * reps in [1, 1000].  Without tuning, tgemm_batched uses threshold 96 and
+ * no packed class.
  */
 int tgemm_batched_autotune(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                            const float* alpha, const void* const* A, const int64_t* lda,
                            const void* const* B, const int64_t* ldb, const float* beta,
                            float* const* C, const int64_t* ldc, int dtype, int reps, void* stream,
-                           int* threshold_out, int* packed_out);
+                           int* threshold_out, int* large_out);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* tgemm_status_string(int status);

@@ -193,13 +193,13 @@ def _arr(ctype, values):
 
 def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None, shape=None):
     """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p.
-    shape: None (tuned or default plan shape) or {"threshold": T, "packed": bool}
+    shape: None (tuned or default plan shape) or {"threshold": T, "large": L}
     (tgemm_batched_with_shape)."""
     args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
     if shape is None:
         _check(lib.tgemm_batched(*args, _stream_handle(stream)), "tgemm_batched")
     else:
-        _check(lib.tgemm_batched_with_shape(*args, int(shape["threshold"]), 1 if shape["packed"] else 0,
+        _check(lib.tgemm_batched_with_shape(*args, int(shape["threshold"]), int(shape["large"]),
                                             _stream_handle(stream)), "tgemm_batched_with_shape")
 
 
@@ -223,12 +223,12 @@ def _batched_args(As, Bs, Cs, alphas, betas, dtype):
 
 def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream=None):
     """Plan-shape tuning of a grouped set (tgemm_batched_autotune); returns
-    {"threshold": T, "packed": bool} (T = 2**31 - 1: 64x64 tiles everywhere)."""
+    {"threshold": T, "large": L} (2**31 - 1: never)."""
     args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
-    thr, packed = ctypes.c_int32(), ctypes.c_int32()
+    thr, large = ctypes.c_int32(), ctypes.c_int32()
     _check(lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream), ctypes.byref(thr),
-                                      ctypes.byref(packed)), "tgemm_batched_autotune")
-    return {"threshold": thr.value, "packed": bool(packed.value)}
+                                      ctypes.byref(large)), "tgemm_batched_autotune")
+    return {"threshold": thr.value, "large": large.value}
 
 
 def set_policy(policy):

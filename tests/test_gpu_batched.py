@@ -35,11 +35,12 @@ def _problem_set(dims, seed_base, integer=False):
 
 
 NEVER = 2**31 - 1
-# plan shapes: the default (tuned or built-in), and forced packed / direct operands with
-# mixed, all-128 and all-64 macro-tiles
-SHAPES = [None] + [{"threshold": t, "packed": pk} for pk in (True, False) for t in (96, 0, NEVER)]
-SHAPE_IDS = ["default"] + [f"{'packed' if pk else 'direct'}-{t if t != NEVER else 'all64'}"
-                           for pk in (True, False) for t in (96, 0, NEVER)]
+# plan shapes: the default (tuned or built-in); direct tiles only (mixed, all 128, all 64);
+# packed 256 x 256 tiles for the larger problems; packed tiles for every problem
+SHAPES = [None, {"threshold": 96, "large": NEVER}, {"threshold": 0, "large": NEVER},
+          {"threshold": NEVER, "large": NEVER}, {"threshold": 96, "large": 200},
+          {"threshold": NEVER, "large": 0}]
+SHAPE_IDS = ["default", "direct-mixed", "direct-128", "direct-64", "hybrid", "packed-all"]
 
 
 def _run_batched(tg, host, alphas, betas, dtype, shape=None):
@@ -71,8 +72,8 @@ def test_small_set_bit_exact_on_integers(tg, dtype, shape):
         np.testing.assert_array_equal(g.numpy().astype(np.float64), ref, err_msg=f"problem {p} {dims[p]}")
 
 
-@pytest.mark.parametrize("packed", [True, False])
-def test_alpha_zero_and_padded_strides(tg, packed):
+@pytest.mark.parametrize("large", [0, NEVER])
+def test_alpha_zero_and_padded_strides(tg, large):
     # alpha == 0 must not read A (NaN there), and row strides wider than the matrices
     # (unaligned and aligned) take the 4-byte and 16-byte load configurations.
     dims = [(40, 50, 30), (200, 160, 120), (129, 257, 65), (96, 96, 96)]
@@ -90,7 +91,7 @@ def test_alpha_zero_and_padded_strides(tg, packed):
         views.append(Cd)
     As[0] = torch.full_like(As[0], float("nan"))
     alphas, betas = [0.0, 1.0, 1.0, 2.0], [0.5, 0.5, 0.0, 1.0]
-    tg.gemm_batched(As, Bs, Cs, alphas, betas, "f32", shape={"threshold": 96, "packed": packed})
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, "f32", shape={"threshold": 96, "large": large})
     torch.cuda.synchronize()
     np.testing.assert_array_equal(Cs[0].cpu().numpy(), (0.5 * host[0][2]).numpy())
     for p in range(1, 4):
@@ -99,7 +100,7 @@ def test_alpha_zero_and_padded_strides(tg, packed):
         assert torch.isnan(views[p][:, host[p][2].shape[1]:]).all()    # canaries intact
 
 
-@pytest.mark.parametrize("shape", [None, {"threshold": 96, "packed": False}], ids=["default", "direct"])
+@pytest.mark.parametrize("shape", [None, {"threshold": 96, "large": NEVER}], ids=["default", "direct"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_grouped_config_512_problems(tg, dtype, shape):
     # 512 problems, M, N, K log-uniform in [16, 2048] (seed 4), matrices from seeds
@@ -116,8 +117,8 @@ def test_grouped_config_512_problems(tg, dtype, shape):
     assert worst <= 1e-5
 
 
-@pytest.mark.parametrize("packed", [True, False])
-def test_graph_capture_replays_match_eager(tg, packed):
+@pytest.mark.parametrize("large", [200, NEVER])
+def test_graph_capture_replays_match_eager(tg, large):
     rng = np.random.default_rng(52)
     dims = rng.integers(16, 400, size=(40, 3))
     host = _problem_set(dims, 5200)
@@ -126,7 +127,7 @@ def test_graph_capture_replays_match_eager(tg, packed):
     Bs = [h[1].to(DEV) for h in host]
     Cg = [h[2].clone().to(DEV) for h in host]        # graph-updated
     Ce = [h[2].clone().to(DEV) for h in host]        # eager-updated
-    shape = {"threshold": 96, "packed": packed}
+    shape = {"threshold": 96, "large": large}
     # plan exists before capture (first call plans; it also advances Cg once)
     tg.gemm_batched(As, Bs, Cg, alphas, betas, "x3", shape=shape)
     tg.gemm_batched(As, Bs, Ce, alphas, betas, "x3", shape=shape)
@@ -193,7 +194,7 @@ def test_autotune_restores_c_and_tuned_plan_is_exact(tg, dtype):
     t = tg.gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype, reps=2)
     torch.cuda.synchronize()
     print(f"{dtype}: tuned threshold {t}", flush=True)
-    assert t["threshold"] in (0, 64, 96, 160, 256, 512, 2**31 - 1) and t["packed"] in (True, False)
+    assert t["threshold"] in (0, 64, 96, 160, 256, 512, NEVER) and t["large"] in (256, 512, 1024, NEVER)
     for p, (b, c) in enumerate(zip(before, Cs)):
         assert torch.equal(b, c), f"C of problem {p} not restored"
     tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
@@ -209,4 +210,4 @@ def test_autotune_and_forced_shape_reject_bad_arguments(tg):
     with pytest.raises(tg.TgemmError):
         tg.gemm_batched_autotune([A], [A], [A.clone()], [1.0], [0.0], "f32", reps=0)
     with pytest.raises(tg.TgemmError):
-        tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "packed": True})
+        tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "large": 0})
