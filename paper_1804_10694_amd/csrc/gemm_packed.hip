@@ -71,6 +71,12 @@ const PSched kPacked[] = {
     // two workgroups per CU (LDS <= 80 KB), 4 waves each
     TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 32, 2, 2, 2),
     TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 4),
+    // four workgroups per CU (LDS 32 KB): one wave of 128 x 128 tiles covers
+    // 1024 tiles, for problems whose tile count falls just past 512
+    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 2),
+    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 16, 2, 2, 2),
+    TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 32, 2, 2, 2),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 64, 2, 2, 2),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 16, 2, 2, 3),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 128, 32, 2, 2, 3),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 128, 64, 2, 2, 3),

@@ -110,12 +110,12 @@ bool dense_vec_ok(int64_t N, int64_t K, int dtype)
     return (K * es) % 16 == 0 && (N * es) % 16 == 0;
 }
 
-int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN)
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds)
 {
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec &&
-            d.WGM == WGM && d.WGN == WGN)
+            d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds))
             return i;
     }
     return -1;
@@ -159,20 +159,23 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
         out->xcd_remap = 1;
         return TGEMM_SUCCESS;
     };
-    // Large F32 problems: packed operands, 128 x 128 macro-tiles, four LDS
-    // stages (measured on MI355X: 138 TFLOP/s at 8192^3 against 122 for the
-    // best direct schedule; the packing pass costs O(MK + KN) against O(MNK)).
-    if (dtype == TGEMM_F32 && K >= 512 && tiles(128, 128) >= 192) {
-        const int id = find_schedule(dtype, 128, 128, 16, 0, 2, 2);
-        if (id >= 0) return take(id);
-    }
-    // Large 16/8-bit problems: packed operands with 256 x 256 macro-tiles and 8
-    // waves.
-    if (dtype != TGEMM_F32 && K >= 512) {
-        const int bk = dtype == TGEMM_F32_BF16X3 ? 32 : (dtype == TGEMM_BF16 ? 64 : 128);
+    // Large problems take packed operands (the packing pass costs O(MK + KN)
+    // against O(MNK)).  Measured on MI355X:
+    //  - f32 and e4m3: 128 x 128 macro-tiles, two 32 KB LDS stages, four
+    //    workgroups per CU (f32 139 TFLOP/s at 8192^3 against 122 for the best
+    //    direct schedule; e4m3 1120 TFLOP/s at 16384^3 against 1030 for 256 x
+    //    256 tiles: the extra workgroups keep more panel loads in flight);
+    //  - x3 and bf16: 256 x 256 macro-tiles of 8 waves.
+    if (K >= 512) {
         int id = -1;
-        if (tiles(256, 256) >= 256) id = find_schedule(dtype, 256, 256, bk, 0, 2, 4);
-        else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, bk, 0, 2, 2);
+        if (dtype == TGEMM_F32 || dtype == TGEMM_FP8_E4M3) {
+            const int bk = dtype == TGEMM_F32 ? 16 : 64;
+            if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, bk, 0, 2, 2, 32768);
+        } else {
+            const int bk = dtype == TGEMM_F32_BF16X3 ? 32 : 64;
+            if (tiles(256, 256) >= 256) id = find_schedule(dtype, 256, 256, bk, 0, 2, 4);
+            else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, bk, 0, 2, 2);
+        }
         if (id >= 0) return take(id);
     }
     return direct_schedule(M, N, K, dtype, vec_allowed, out);

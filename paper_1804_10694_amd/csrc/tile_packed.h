@@ -235,11 +235,7 @@ template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_>
 struct PCfg {
     static constexpr int MODE = MODE_, BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
     static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
-    // waves per SIMD the register allocation must allow: two workgroups per CU
-    // when one workgroup's LDS fits in half of the 160 KB
     static constexpr int ES = (MODE == MODE_FP8) ? 1 : (MODE == MODE_F32) ? 4 : 2;  // bytes
-    static constexpr int WAVES_PER_EU =
-        (NS_ * (MODE_ == MODE_X3 ? 2 : 1) * (BM_ + BN_) * BK_ * ES <= 80 * 1024 && WGM_ * WGN_ == 4) ? 2 : 1;
     static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
     static constexpr int KU = 16 / ES;                   // k per 16-byte unit
     static constexpr int UK = BK / KU;                   // units per packed row per panel
@@ -253,6 +249,11 @@ struct PCfg {
     static constexpr int LDS_A = BM * UK * 16, LDS_B = BN * UK * 16;
     static constexpr int LDS_STAGE = NARR * (LDS_A + LDS_B);
     static constexpr int LDS_BYTES = NS * LDS_STAGE;
+    // waves per SIMD the register allocation must allow: the workgroups whose
+    // LDS fits in a CU's 160 KB, NW / 4 waves per SIMD each, at most four
+    static constexpr int WG_PER_CU = (160 * 1024) / LDS_BYTES;
+    static constexpr int WAVES_PER_EU =
+        (NW / 4) * WG_PER_CU > 4 ? 4 : ((NW / 4) * WG_PER_CU < 1 ? 1 : (NW / 4) * WG_PER_CU);
     // direct-to-LDS instructions (64 units each) per wave per array per panel
     static constexpr int A_INSTR = BM * UK / 64 / NW, B_INSTR = BN * UK / 64 / NW;
     static constexpr int LOADS_PER_STAGE = NARR * (A_INSTR + B_INSTR);

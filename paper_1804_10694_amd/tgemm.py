@@ -256,10 +256,11 @@ def schedules(dtype=None):
 
 
 def schedule_key(sid):
-    """Readable name of a compiled schedule: dtype, tile sizes, wave grid, load width."""
+    """Readable, unique name of a compiled schedule: dtype, tile sizes, wave grid, load
+    width (vec0: packed operands) and LDS bytes (which tell the pipeline depths apart)."""
     i = schedule_info(sid)
     return (f"sched:{i['dtype']}:{i['BM']}x{i['BN']}x{i['BK']}:{i['WGM']}x{i['WGN']}:"
-            f"vec{i['vec']}")
+            f"vec{i['vec']}:lds{i['lds_bytes']}")
 
 
 def tile_map(M, N, BM, BN, group_m, xcd_remap):

@@ -138,3 +138,8 @@ def test_select_schedule_serves_dtype(tg):
             sid, gm, xcd = tg.select_schedule(*shape, dt)
             assert tg.schedule_info(sid)["dtype"] == tg.DTYPES[dt]
             assert gm >= 1
+
+
+def test_schedule_keys_are_unique(tg):
+    keys = [tg.schedule_key(i) for i in range(tg.schedule_count())]
+    assert len(keys) == len(set(keys))
