@@ -94,6 +94,22 @@ def test_aligned_multi_tile_exact(tg, dtype):
                                       err_msg=f"schedule {sid} {info}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_packed_schedules_exact_with_vector_packing(tg, dtype):
+    # Rows whose strides allow the packing pass's 16-byte loads (the "align4" padding),
+    # ragged in M and N, K = 100 (the last group of 8 k falls back to element loads) and
+    # K = 96 (every group is a vector load), with NaN canaries around every matrix.
+    for (M, N, K) in [(300, 200, 100), (260, 130, 96)]:
+        A, B, C0 = inputs.integer_inputs(M, N, K, seed=12 + K)
+        ref = oracle.gemm(A, B, C0, 1.0, 0.5)
+        for sid, info in _serving(tg, dtype, vec=0):
+            print(f"packed schedule {sid} {info} M={M} N={N} K={K}", flush=True)
+            got, ok = _run(tg, A, B, C0, 1.0, 0.5, dtype, sid, ld_pad="align4")
+            assert ok, f"canary overwritten by schedule {sid}"
+            np.testing.assert_array_equal(got.numpy().astype(np.float64), ref,
+                                          err_msg=f"schedule {sid} {info} {(M, N, K)}")
+
+
 def test_brute_force_tiny_sizes(tg):
     # All small (M, N) with a ladder of K values, default policy, integer inputs.
     Ks = [1, 2, 3, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129]
