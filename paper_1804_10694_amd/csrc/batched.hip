@@ -684,6 +684,12 @@ extern "C" int tgemm_batched_autotune(int64_t count, const int64_t* M, const int
             const Shape cand{threshold, large};
             Plan plan;
             rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cand, &plan);
+            if (rc == TGEMM_ALLOC_FAILED && large != kNever) {
+                // no room for this shape's packing workspace: not a candidate
+                free_plan(plan);
+                rc = TGEMM_SUCCESS;
+                continue;
+            }
             if (rc != TGEMM_SUCCESS) {
                 free_plan(plan);
                 break;
