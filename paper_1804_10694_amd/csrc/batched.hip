@@ -348,7 +348,9 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         g.alpha = alpha[p];
         g.beta = beta[p];
         g.scale_only = (K[p] == 0 || alpha[p] == 0.f) ? 1 : 0;
-        const bool pk = !g.scale_only && reaches(g, shape.large);
+        // the packed class needs a tile's 256 packed rows to span under 2^31 bytes
+        const bool pk = !g.scale_only && reaches(g, shape.large) &&
+                        (int64_t)kPackedTile * round_up(g.K, kPackedKPad) * 4 <= INT32_MAX;
         int t = 64;
         if (pk) {
             t = kPackedTile;

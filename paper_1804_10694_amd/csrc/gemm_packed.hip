@@ -177,11 +177,19 @@ void packed_shutdown()
 }
 
 // Pack A and B into `ws` and run packed schedule `pid` (index into kPacked).
+bool packed_k_ok(int64_t K, int dtype)
+{
+    const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
+    const int64_t es = dtype == TGEMM_FP8_E4M3 ? 1 : dtype == TGEMM_F32 ? 4 : 2;
+    return kPackRows * Kp * es <= INT32_MAX;
+}
+
 int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
                   const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                   int64_t ldc, int group_m, int xcd_remap, void* ws, hipStream_t s)
 {
     const PSched& p = kPacked[pid];
+    if (!packed_k_ok(K, p.dtype)) return TGEMM_NOT_SUPPORTED;
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
@@ -254,6 +262,7 @@ int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void
                const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                int64_t ldc, int group_m, int xcd_remap, hipStream_t s)
 {
+    if (!packed_k_ok(K, kPacked[pid].dtype)) return TGEMM_NOT_SUPPORTED;
     void* ws = nullptr;
     const int rc = packed_workspace(s, packed_workspace_bytes(M, N, K, kPacked[pid].dtype), &ws);
     if (rc != TGEMM_SUCCESS) return rc;

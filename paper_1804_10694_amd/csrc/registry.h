@@ -25,13 +25,17 @@ const SchedDesc& schedule(int id);
 // Per-translation-unit tables.
 const SchedDesc* tile_schedules(int* n);    // F32 and split-bf16x3
 const SchedDesc* scaled_schedules(int* n);  // bf16 and fp8 with per-tile scales
-const SchedDesc* packed_schedules(int* n);  // packed-operand x3, bf16, fp8
+const SchedDesc* packed_schedules(int* n);  // packed-operand f32, x3, bf16, fp8
 
 // Packed schedules (gemm_packed.hip): index within packed_schedules().
 int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
                const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                int64_t ldc, int group_m, int xcd_remap, hipStream_t s);
 size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype);
+// Whether the packed kernels can address a problem of depth K: a tile's packed
+// rows (256 of them, Kp elements each) must span fewer than 2^31 bytes, the
+// reach of a buffer resource's 32-bit offsets.
+bool packed_k_ok(int64_t K, int dtype);
 void packed_shutdown();
 void packed_release(hipStream_t s);  // frees the workspace of one stream
 // Position of a schedule id inside packed_schedules(), or -1.

@@ -170,7 +170,7 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    extra workgroups keep more panel loads in flight);
     //  - x3 and bf16: 256 x 256 macro-tiles of 8 waves, down to half a wave
     //    of tiles (one workgroup per CU still beats 128 x 128 tiles there).
-    if (K >= 512) {
+    if (K >= 512 && packed_k_ok(K, dtype)) {
         int id = -1;
         if (dtype == TGEMM_F32) {
             if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);

@@ -250,3 +250,22 @@ def test_full_size_configs_sampled(tg, shape, seed):
         print(f"{dtype} {shape} sampled-row normwise error {err:.3e}")
         assert err <= TOL
         del Cd
+
+
+def test_deep_k_beyond_packed_reach(tg):
+    # K = 2^21 + 3: a 256-row packed f32 tile would span more than 2^31 bytes, past
+    # the 32-bit offsets of the buffer loads.  A forced packed schedule is refused
+    # (no launch); the default rule takes a direct schedule, exact on integer inputs.
+    M, N, K = 8, 8, (1 << 21) + 3
+    g = torch.Generator().manual_seed(41)
+    A = torch.randint(-2, 3, (M, K), generator=g).float()
+    B = torch.randint(-2, 3, (K, N), generator=g).float()
+    C0 = torch.zeros(M, N)
+    ref = oracle.gemm(A, B, C0, 1.0, 0.0)   # |partial sums| <= 4 * 2^21 < 2^24: exact
+    packed = [sid for sid, info in _serving(tg, "f32", vec=0)]
+    Ad, Bd, Cd = A.to(DEV), B.to(DEV), C0.to(DEV)
+    with pytest.raises(tg.TgemmError):
+        tg.gemm_with_schedule(Ad, Bd, Cd, 1.0, 0.0, "f32", packed[0], 8, 1)
+    tg.gemm(Ad, Bd, Cd, 1.0, 0.0, "f32")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(Cd.cpu().numpy().astype(np.float64), ref)
