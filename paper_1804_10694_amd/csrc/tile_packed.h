@@ -312,6 +312,21 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
+// Workgroup barrier of the panel pipeline.  It carries no memory fence: a
+// workgroup fence would make every wave wait for all of its outstanding loads
+// (vmcnt(0)), including the panels issued ahead, and collapse the pipeline to
+// one panel in flight.  Ordering comes from the explicit vmcnt wait before it
+// (this wave's loads of the panel have reached LDS), the barrier itself (every
+// wave's have), and the compiler barriers, which keep LDS reads and the next
+// loads on their side of it.  The previous panel's LDS reads are complete at
+// the barrier: their MFMAs, which consume them, come before it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 struct PackedArgs {
     const char* A;    // packed A (hi), Rp_a x Kp
     const char* Alo;  // x3: packed A lo
@@ -507,7 +522,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         // and frees the stage that panel s - 1 occupied
         if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * CF::LOADS_PER_STAGE>();
         else wait_vmcnt<0>();
-        __syncthreads();
+        lds_barrier();
         if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
         if (scaled) {
             const int kb = (s * CF::BK) / 128;
