@@ -327,6 +327,9 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("" ::: "memory");
 }
 
+// This wave's LDS reads (and scalar loads) complete.
+__device__ __forceinline__ void wait_lds_reads() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 struct PackedArgs {
     const char* A;    // packed A (hi), Rp_a x Kp
     const char* Alo;  // x3: packed A lo
@@ -513,34 +516,82 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     };
 
     // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
-    constexpr int NS = CF::NS;
+    constexpr int NS = CF::NS, L = CF::LOADS_PER_STAGE;
     for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
     int kb_cur = 0;
-    for (int s = 0; s < npanel; ++s) {
-        // this wave's loads of panel s have landed once at most the loads of the
-        // panels issued after it remain; then the barrier covers every wave's loads
-        // and frees the stage that panel s - 1 occupied
-        if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * CF::LOADS_PER_STAGE>();
+    // new K scale block at panel s: keep acc divided by the current scale product
+    auto rescale = [&](int s) {
+        if (!scaled) return;
+        const int kb = (s * CF::BK) / 128;
+        if (s == 0 || kb == kb_cur) return;
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+                const float ratio = block_scale(a, r0, c0, kb_cur) / block_scale(a, r0, c0, kb);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+            }
+        kb_cur = kb;
+    };
+    if (NS == 2) {
+        for (int s = 0; s < npanel; ++s) {
+            // this wave's loads of panel s have landed once at most the loads of the
+            // panels issued after it remain; then the barrier covers every wave's loads
+            // and frees the stage that panel s - 1 occupied
+            if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * L>();
+            else wait_vmcnt<0>();
+            lds_barrier();
+            if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
+            rescale(s);
+            pk_mma<CF>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+        }
+    } else {
+        // Three or more stages: the next panel has landed before this one ends, so
+        // the first group of its operands is read from LDS while the last group of
+        // this panel runs on the MFMAs; neither the barrier nor the LDS latency of a
+        // panel boundary leaves the matrix cores idle.  The barrier that admits
+        // panel s + 1 follows this wave's last LDS read of panel s, so the refill of
+        // panel s's stage (issued after it, at the top of the next iteration) never
+        // overtakes a read.
+        constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
+        constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
+        constexpr int NPAIR = NREAD < NMFMA ? NREAD : NMFMA;
+        PkOps<CF> ops[2];
+        if (NS - 2 < npanel) wait_vmcnt<(NS - 2) * L>();
         else wait_vmcnt<0>();
         lds_barrier();
-        if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
-        if (scaled) {
-            const int kb = (s * CF::BK) / 128;
-            if (s > 0 && kb != kb_cur) {
-                // new K scale block: keep acc divided by the current scale product
+        pk_load<CF>(lds, ops[0], 0, wm0, wn0, lane);
+        for (int s = 0; s < npanel; ++s) {
+            if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
+            rescale(s);
+            const char* stage = lds + (s % NS) * CF::LDS_STAGE;
 #pragma unroll
-                for (int i = 0; i < CF::TM; ++i)
+            for (int g = 0; g < CF::NG; ++g) {
+                bool read = false;
+                if (g + 1 < CF::NG) {
+                    pk_load<CF>(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
+                    read = true;
+                } else if (s + 1 < npanel) {
+                    if (s + NS - 1 < npanel) wait_vmcnt<(NS - 2) * L>();
+                    else wait_vmcnt<0>();
+                    wait_lds_reads();
+                    lds_barrier();
+                    pk_load<CF>(lds + ((s + 1) % NS) * CF::LDS_STAGE, ops[CF::NG & 1], 0, wm0, wn0, lane);
+                    read = true;
+                }
+                pk_compute<CF>(ops[g & 1], acc);
+                if (read) {
 #pragma unroll
-                    for (int j = 0; j < CF::TN; ++j) {
-                        const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
-                        const float ratio = block_scale(a, r0, c0, kb_cur) / block_scale(a, r0, c0, kb);
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                    for (int k = 0; k < NPAIR; ++k) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
                     }
-                kb_cur = kb;
+                }
             }
+            if (CF::NG & 1) ops[0] = ops[1];  // the next panel's first group
         }
-        pk_mma<CF>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
     }
 
     const int h = lane >> 5, l32 = lane & 31;
