@@ -14,7 +14,10 @@ Contents
   normwise_error  ||X - R||_F / ||R||_F in FP64.
   mlp             FP64 ReLU MLP, MSE loss, chain-rule gradients and Adam
                   (the cost model's network).
+  conv            FP64 3x3 'same' convolution layer, NHWC (the Conv layer
+                  of Section VI-A as an implicit gemm's reference).
 """
 from .gemm import gemm, gemm_rows, num_threads, normwise_error, lib_path  # noqa: F401
 from . import precision  # noqa: F401
 from . import mlp  # noqa: F401
+from . import conv  # noqa: F401

@@ -343,3 +343,82 @@ def test_adam_first_step_closed_form():
     p, m, v = O.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+# ------------------------------------------------------------------ 3x3 convolution oracle
+from oracle import conv as OC  # noqa: E402
+
+
+def _int_conv_inputs(nb, H, W, cin, cout, seed):
+    g = np.random.default_rng(seed)
+    return (g.integers(-3, 4, (nb, H, W, cin)).astype(np.float64),
+            g.integers(-3, 4, (3, 3, cin, cout)).astype(np.float64),
+            g.integers(-3, 4, (nb, H, W, cout)).astype(np.float64))
+
+
+def test_conv_brute_force_tiny():
+    # every output element by its own six-deep loop, with the padding as an explicit bounds test
+    X, Wt, Y0 = _int_conv_inputs(2, 3, 4, 2, 3, seed=61)
+    nb, H, W, cin = X.shape
+    cout = Wt.shape[3]
+    ref = np.zeros((nb, H, W, cout))
+    for n in range(nb):
+        for y in range(H):
+            for x in range(W):
+                for co in range(cout):
+                    s = 0.0
+                    for dy in range(3):
+                        for dx in range(3):
+                            iy, ix = y + dy - 1, x + dx - 1
+                            if 0 <= iy < H and 0 <= ix < W:
+                                for ci in range(cin):
+                                    s += X[n, iy, ix, ci] * Wt[dy, dx, ci, co]
+                    ref[n, y, x, co] = 1.5 * s + 0.5 * Y0[n, y, x, co]
+    np.testing.assert_array_equal(OC.conv3x3(X, Wt, Y0, 1.5, 0.5), ref)
+
+
+def test_conv_center_tap_identity_is_copy():
+    X, _, _ = _int_conv_inputs(2, 5, 6, 4, 4, seed=62)
+    Wt = np.zeros((3, 3, 4, 4))
+    Wt[1, 1] = np.eye(4)
+    np.testing.assert_array_equal(OC.conv3x3(X, Wt), X)
+
+
+def test_conv_delta_input_echoes_the_flipped_filter():
+    # a single 1 at (n, y, x, c): output pixel (y + 1 - dy, x + 1 - dx) receives Wt[dy, dx, c, :]
+    _, Wt, _ = _int_conv_inputs(1, 1, 1, 3, 5, seed=63)
+    X = np.zeros((1, 6, 7, 3))
+    X[0, 3, 2, 1] = 1.0
+    Y = OC.conv3x3(X, Wt)
+    expect = np.zeros_like(Y)
+    for dy in range(3):
+        for dx in range(3):
+            expect[0, 3 + 1 - dy, 2 + 1 - dx] = Wt[dy, dx, 1]
+    np.testing.assert_array_equal(Y, expect)
+
+
+def test_conv_equals_gemm_on_explicit_im2col():
+    # an independent construction: the im2col matrix built element by element, then the gemm oracle
+    X, Wt, Y0 = _int_conv_inputs(2, 4, 5, 3, 6, seed=64)
+    nb, H, W, cin = X.shape
+    cols = np.zeros((nb * H * W, 9 * cin))
+    for n in range(nb):
+        for y in range(H):
+            for x in range(W):
+                for t in range(9):
+                    iy, ix = y + t // 3 - 1, x + t % 3 - 1
+                    if 0 <= iy < H and 0 <= ix < W:
+                        cols[(n * H + y) * W + x, t * cin:(t + 1) * cin] = X[n, iy, ix]
+    ref = oracle.gemm(cols, Wt.reshape(9 * cin, -1), Y0.reshape(nb * H * W, -1), 1.0, 2.0)
+    np.testing.assert_array_equal(OC.conv3x3(X, Wt, Y0, 1.0, 2.0).reshape(nb * H * W, -1), ref)
+
+
+def test_conv_pixel_subset_and_degenerate_scalars():
+    X, Wt, Y0 = _int_conv_inputs(2, 4, 5, 3, 6, seed=65)
+    full = OC.conv3x3(X, Wt, Y0, 1.0, 0.5).reshape(40, 6)
+    pix = [0, 7, 19, 20, 39]
+    np.testing.assert_array_equal(OC.conv3x3(X, Wt, Y0, 1.0, 0.5, pixels=pix), full[pix])
+    # beta == 0 does not read Y0; alpha == 0 gives beta * Y0
+    nan = np.full_like(Y0, np.nan)
+    assert np.isfinite(OC.conv3x3(X, Wt, nan, 1.0, 0.0)).all()
+    np.testing.assert_array_equal(OC.conv3x3(X, Wt, Y0, 0.0, 0.5), 0.5 * Y0)
