@@ -19,6 +19,8 @@ The extra_rows leg (outside the step and its value) measures the other rows of
 the path on their own workloads:
   - per-128x128-tile scaled gemm at 16384^3 (A, B ~ N(0,1) with 1% of rows x1e3,
     seed 30), quantised on the GPU, e4m3 and bf16, alpha = 1, beta = 0;
+  - a 3x3 convolution layer (batch 32, 56 x 56, 256 -> 256 channels, NHWC, seed 5) as an
+    implicit gemm, F32 and split-bf16x3, beside a materialised im2col matrix fed to the gemm;
   - the grouped persistent launch over 512 problems with M, N, K log-uniform in
     [16, 2048] (seed 4, matrices from seeds 4000 + p), alpha = 1, beta = 0.5,
     F32 and split-bf16x3, tile shapes tuned on the set (tgemm_batched_autotune),
@@ -159,6 +161,34 @@ def extra_rows(tg, inputs):
             "algorithmic_bytes": 2 * n * n * es + 4 * n * n}
         del qa, qb
     del Ad, Bd, C
+    torch.cuda.empty_cache()
+
+    # 3x3 convolution layer as an implicit gemm, against a materialised im2col matrix
+    # (built with torch ops) fed to the gemm
+    nb, H, W, cin, cout = 32, 56, 56, 256, 256
+    X, Wt, Y0 = (t.to(dev) for t in inputs.conv_layer_inputs(nb, H, W, cin, cout, 5))
+    cflops = 2.0 * nb * H * W * cout * 9 * cin
+    for dt in ("f32", "x3"):
+        Y = Y0.clone()
+        avg, med = _time_events(lambda: tg.conv3x3(X, Wt, Y, 1.0, 0.0, dt), 10)
+
+        def im2col():
+            Xp = torch.nn.functional.pad(X, (0, 0, 1, 1, 1, 1))
+            return torch.cat([Xp[:, dy:dy + H, dx:dx + W, :] for dy in range(3) for dx in range(3)],
+                             dim=3).reshape(nb * H * W, 9 * cin)
+        cols = im2col()
+        Wm = Wt.reshape(9 * cin, cout)
+        Ym = Y0.reshape(nb * H * W, cout).clone()
+        i_avg, _ = _time_events(im2col, 5)
+        g_avg, _ = _time_events(lambda: tg.gemm(cols, Wm, Ym, 1.0, 0.0, dt), 10)
+        out[f"conv3x3_{dt}_b32_56x56_256"] = {
+            "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(cflops / (avg * 1e-3) / 1e12, 2),
+            "peak_tflops": round(PEAK_TFLOPS[dt], 1),
+            "frac_peak": round(cflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4),
+            "im2col_materialised_ms": round(i_avg, 4), "gemm_on_im2col_ms": round(g_avg, 4),
+            "implicit_over_materialised": round((i_avg + g_avg) / avg, 3)}
+        del cols, Ym, Y
+    del X, Wt, Y0
     torch.cuda.empty_cache()
 
     dims = inputs.grouped_dims()

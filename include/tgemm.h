@@ -141,6 +141,27 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
                   float* const* C, const int64_t* ldc, int dtype, void* stream);
 
 /*
+ * 3x3 convolution layer as an implicit gemm (project addition; the paper's
+ * Conv benchmark layer, Section VI-A, which builds convolutions on sgemm):
+ *   Y[n, y, x, co] = alpha * sum_{dy, dx, ci} Xpad[n, y + dy, x + dx, ci] * Wt[dy, dx, ci, co]
+ *                    + beta * Y[n, y, x, co]
+ * with stride 1 and zero padding 1 (Xpad: X with a border of zeros), so Y
+ * has X's height and width.  Layouts (all DEVICE pointers, dense):
+ *   X  batch x H x W x Cin (NHWC) float, 16-byte aligned;
+ *   Wt 3 x 3 x Cin x Cout float (a 9*Cin x Cout row-major matrix);
+ *   Y  batch x H x W x Cout (NHWC) float.
+ * The im2col matrix (batch*H*W x 9*Cin) is never formed: tiles read their
+ * input pixels directly.  dtype: TGEMM_F32 or TGEMM_F32_BF16X3 (the x3 form
+ * of every product).  Cin must be a multiple of 4 (f32) or 8 (x3) and X
+ * 16-byte aligned, else TGEMM_NOT_SUPPORTED; sizes beyond 32-bit indexing
+ * (batch*H*W, 9*Cin, Cout) give TGEMM_NOT_SUPPORTED.  Degenerate cases as for
+ * tgemm: batch, H, W or Cout == 0 is a no-op; Cin == 0 or alpha == 0 gives
+ * Y = beta*Y without reading X or Wt; beta == 0 does not read Y.
+ */
+int tgemm_conv3x3(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
+                  const float* X, const float* Wt, float beta, float* Y, int dtype, void* stream);
+
+/*
  * tgemm_batched with the plan shape fixed by the caller instead of tuned or
  * defaulted (project addition).  Problems whose M and N both reach `large`
  * (>= 0; INT32_MAX: none) take the packed path: a packing pass copies their A

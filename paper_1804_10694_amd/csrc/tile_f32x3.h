@@ -88,23 +88,36 @@ template <int KU> struct UnitVec;
 template <> struct UnitVec<4> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct UnitVec<8> { typedef float type __attribute__((ext_vector_type(8))); };
 
+// Operand geometry of a plain gemm: A and B are the matrices of GemmArgs.
+struct NoGeom {};
+
 template <class CF>
 struct Panel {
     static constexpr int KU = CF::KU, UK = CF::UK, NT = CF::NT, BM = CF::BM, BN = CF::BN;
     static constexpr int BVJ = CF::BVJ;
     typedef typename UnitVec<KU>::type fu;  // the KU float32 values of one unit
+    using Geom = NoGeom;
 
     fu ra[CF::A_PER_T];          // A: one unit (row r, k-unit u) per entry
     fu rb[CF::B_PER_T][BVJ];     // B: already transposed, one unit per column
+
+    // Per-tile set-up of the loads (none for a plain gemm).
+    __device__ __forceinline__ void init(const GemmArgs&, int, int, const Geom&) {}
 
     // Global -> registers for the panel starting at k0.  PRED: per-element
     // bounds checks (partial tiles and the K remainder); out-of-range
     // elements load as zero and are never dereferenced.
     template <bool PRED>
-    __device__ __forceinline__ void load(const GemmArgs& a, int m0, int n0, int k0, int t)
+    __device__ __forceinline__ void load(const GemmArgs& a, int m0, int n0, int k0, int t, const Geom&)
+    {
+        load_a<PRED>(a, m0, k0, t);
+        load_b<PRED>(a, n0, k0, t);
+    }
+
+    template <bool PRED>
+    __device__ __forceinline__ void load_a(const GemmArgs& a, int m0, int k0, int t)
     {
         const float* A = static_cast<const float*>(a.A);
-        const float* B = static_cast<const float*>(a.B);
 #pragma unroll
         for (int p = 0; p < CF::A_PER_T; ++p) {
             const int q = t + p * NT;
@@ -133,6 +146,12 @@ struct Panel {
                 }
             }
         }
+    }
+
+    template <bool PRED>
+    __device__ __forceinline__ void load_b(const GemmArgs& a, int n0, int k0, int t)
+    {
+        const float* B = static_cast<const float*>(a.B);
 #pragma unroll
         for (int p = 0; p < CF::B_PER_T; ++p) {
             const int q = t + p * NT;
@@ -279,8 +298,12 @@ __device__ __forceinline__ void mma_stage(const char* stage, f32x16 (&acc)[CF::T
     }
 }
 
-template <class CF, bool EDGE>
-__device__ __forceinline__ void tile_body(const GemmArgs& a, int m0, int n0, char* lds)
+// PN: the operand loader (Panel for a plain gemm; a loader with its own Geom
+// can compute A's addresses differently, e.g. the implicit im2col of a
+// convolution, and share the rest of the body).
+template <class CF, bool EDGE, class PN = Panel<CF>>
+__device__ __forceinline__ void tile_body(const GemmArgs& a, int m0, int n0, char* lds,
+                                          const typename PN::Geom& geom = typename PN::Geom())
 {
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -298,17 +321,18 @@ __device__ __forceinline__ void tile_body(const GemmArgs& a, int m0, int n0, cha
     const int nfull = a.K / CF::BK;                      // panels with no K remainder
     const int npanel = (a.K + CF::BK - 1) / CF::BK;
 
-    Panel<CF> pn;
-    if (!EDGE && nfull > 0) pn.template load<false>(a, m0, n0, 0, t);
-    else pn.template load<true>(a, m0, n0, 0, t);
+    PN pn;
+    pn.init(a, m0, t, geom);
+    if (!EDGE && nfull > 0) pn.template load<false>(a, m0, n0, 0, t, geom);
+    else pn.template load<true>(a, m0, n0, 0, t, geom);
     pn.store(lds, t);
     __syncthreads();
 
     for (int s = 0; s < npanel; ++s) {
         const int nx = s + 1;
         if (nx < npanel) {
-            if (!EDGE && nx < nfull) pn.template load<false>(a, m0, n0, nx * CF::BK, t);
-            else pn.template load<true>(a, m0, n0, nx * CF::BK, t);
+            if (!EDGE && nx < nfull) pn.template load<false>(a, m0, n0, nx * CF::BK, t, geom);
+            else pn.template load<true>(a, m0, n0, nx * CF::BK, t, geom);
         }
         mma_stage<CF>(lds + (s & 1) * CF::LDS_STAGE, acc, wm0, wn0, lane);
         if (nx < npanel) pn.store(lds + (nx & 1) * CF::LDS_STAGE, t);

@@ -93,6 +93,16 @@ def grouped_inputs(dims, seed_base=4000):
     return out
 
 
+def conv_layer_inputs(batch, H, W, cin, cout, seed):
+    """X (batch, H, W, cin), Wt (3, 3, cin, cout), Y0 (batch, H, W, cout), U[-1, 1] float32,
+    drawn in that order from one seeded generator."""
+    g = _gen(seed)
+    X = uniform(batch * H * W, cin, g).reshape(batch, H, W, cin)
+    Wt = uniform(9 * cin, cout, g).reshape(3, 3, cin, cout)
+    Y0 = uniform(batch * H * W, cout, g).reshape(batch, H, W, cout)
+    return X, Wt, Y0
+
+
 def conv_shapes(batch=32, spatial=(7, 14, 28, 56, 112), channels=(64, 128, 256, 512)):
     """(M, N, K) of the im2col GEMM of every 3x3 conv with Cin, Cout in channels."""
     shapes = []

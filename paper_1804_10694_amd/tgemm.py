@@ -38,6 +38,7 @@ lib.tgemm_scaled.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _p, _i64, _p,
 lib.tgemm_quantize_tiles.argtypes = [_i64, _i64, _p, _i64, _p, _i64, _p, _i32, _p]
 lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32, _pp,
                               _pi64, _i32, _p]
+lib.tgemm_conv3x3.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p]
 lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
                                          _pf32, _pp, _pi64, _i32, _i32, _i32, _p]
 lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
@@ -229,6 +230,22 @@ def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream
     _check(lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream), ctypes.byref(thr),
                                       ctypes.byref(large)), "tgemm_batched_autotune")
     return {"threshold": thr.value, "large": large.value}
+
+
+def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+    """3x3 same-padding convolution as an implicit gemm (tgemm_conv3x3):
+    Y = alpha * conv(X, Wt) + beta * Y, with X (batch, H, W, Cin), Wt (3, 3, Cin, Cout)
+    and Y (batch, H, W, Cout) contiguous float32 device tensors."""
+    import torch
+    for name, t in (("X", X), ("Wt", Wt), ("Y", Y)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    nb, H, W, cin = X.shape
+    if tuple(Wt.shape[:3]) != (3, 3, cin) or tuple(Y.shape) != (nb, H, W, Wt.shape[3]):
+        raise ValueError("shapes must be X (b, H, W, Cin), Wt (3, 3, Cin, Cout), Y (b, H, W, Cout)")
+    _check(lib.tgemm_conv3x3(nb, H, W, cin, Wt.shape[3], alpha, X.data_ptr(), Wt.data_ptr(), beta,
+                             Y.data_ptr(), _dtype_code(dtype), _stream_handle(stream)), "tgemm_conv3x3")
 
 
 def set_policy(policy):
