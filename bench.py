@@ -171,6 +171,7 @@ def extra_rows(tg, inputs):
     for dt in ("f32", "x3"):
         Y = Y0.clone()
         avg, med = _time_events(lambda: tg.conv3x3(X, Wt, Y, 1.0, 0.0, dt), 10)
+        d_avg, _ = _time_events(lambda: tg.conv3x3(X, Wt, Y, 1.0, 0.0, dt, path="direct"), 10)
 
         def im2col():
             Xp = torch.nn.functional.pad(X, (0, 0, 1, 1, 1, 1))
@@ -185,6 +186,7 @@ def extra_rows(tg, inputs):
             "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(cflops / (avg * 1e-3) / 1e12, 2),
             "peak_tflops": round(PEAK_TFLOPS[dt], 1),
             "frac_peak": round(cflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4),
+            "direct_kernel_ms": round(d_avg, 4),
             "im2col_materialised_ms": round(i_avg, 4), "gemm_on_im2col_ms": round(g_avg, 4),
             "implicit_over_materialised": round((i_avg + g_avg) / avg, 3)}
         del cols, Ym, Y

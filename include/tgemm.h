@@ -157,9 +157,44 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
  * (batch*H*W, 9*Cin, Cout) give TGEMM_NOT_SUPPORTED.  Degenerate cases as for
  * tgemm: batch, H, W or Cout == 0 is a no-op; Cin == 0 or alpha == 0 gives
  * Y = beta*Y without reading X or Wt; beta == 0 does not read Y.
+ * Kernel: the packed one (TGEMM_CONV_PACKED below) when X spans fewer than
+ * 2^31 bytes (x3: 2^30 elements), else the direct one; under stream capture
+ * with a workspace too small, the direct one.  Packed tile shape: 0 for f32;
+ * for x3, 1 (256 x 256) when Cout >= 256 and ceil(M/256)*ceil(Cout/256) >=
+ * 256 with M = batch*H*W, else 0.
  */
 int tgemm_conv3x3(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
                   const float* X, const float* Wt, float beta, float* Y, int dtype, void* stream);
+
+/* Kernels of tgemm_conv3x3_path. */
+#define TGEMM_CONV_AUTO 0   /* as tgemm_conv3x3 */
+#define TGEMM_CONV_DIRECT 1 /* A units loaded into registers straight from X; no workspace */
+#define TGEMM_CONV_PACKED 2 /* + i: packed tile shape i of the dtype (tgemm_conv3x3_packed_shape) */
+
+/*
+ * tgemm_conv3x3 with the kernel chosen by the caller (project addition).
+ * TGEMM_CONV_DIRECT: the gemm tile body with register-staged loads, each
+ * 16-byte unit of the im2col matrix read from its input pixel (zero in the
+ * padding).  TGEMM_CONV_PACKED + i: the filter is packed once into a
+ * library-owned workspace of K-contiguous rows (array packing, Section I;
+ * x3 also splits X into bf16 high and low parts there), and an LDS pipeline
+ * brings A panels in with per-lane buffer loads from the input pixels.  The
+ * workspace is the per-(device, stream) one of tgemm; it is not grown under
+ * stream capture (TGEMM_CAPTURE_UNPLANNED).  Returns TGEMM_INVALID_VALUE for
+ * an unknown path and TGEMM_NOT_SUPPORTED when the packed kernel cannot
+ * address the problem (X or one 256-row block of packed filter rows of
+ * 2^31 bytes or more); otherwise as tgemm_conv3x3.
+ */
+int tgemm_conv3x3_path(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
+                       const float* X, const float* Wt, float beta, float* Y, int dtype, int path,
+                       void* stream);
+
+/*
+ * Macro-tile (bm x bn), K panel (bk) and LDS pipeline depth (stages) of packed
+ * conv tile shape i for dtype (host pointers; any may be NULL).  No HIP call.
+ * TGEMM_INVALID_VALUE past the last shape or for a dtype without one.
+ */
+int tgemm_conv3x3_packed_shape(int dtype, int i, int* bm, int* bn, int* bk, int* stages);
 
 /*
  * tgemm_batched with the plan shape fixed by the caller instead of tuned or

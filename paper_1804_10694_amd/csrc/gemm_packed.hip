@@ -19,9 +19,6 @@
 
 namespace tg {
 
-constexpr int kPackRows = 256;  // packed row counts are multiples of this
-constexpr int kPackK = 128;     // packed K is a multiple of this (elements)
-
 // ------------------------------------------------------------------ kernels
 // Groups of 8 k are numbered row by row; fewer than 2^32 of them (checked on
 // the host), so the row and column come from one 32-bit division.
@@ -176,6 +173,59 @@ void packed_shutdown()
     g_ws.clear();
 }
 
+namespace {
+template <int MODE>
+void pack_rows_mode(const void* X, int64_t ldx, int R, int K, void* P, void* Plo, int Rp, int Kp, int vec,
+                    unsigned grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_rows_kernel<MODE>, dim3(grid), dim3(256), 0, s, X, ldx, R, K, P, Plo, Rp, Kp, vec);
+}
+template <int MODE>
+void pack_cols_mode(const void* X, int64_t ldx, int K, int N, void* P, void* Plo, int Np, int Kp, int vec,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_cols_kernel<MODE>, dim3((unsigned)(Np / 64), (unsigned)(Kp / 64)), dim3(256), 0, s,
+                       X, ldx, K, N, P, Plo, Np, Kp, vec);
+}
+int mode_elem_bytes(int mode) { return mode == MODE_FP8 ? 1 : mode == MODE_BF16 ? 2 : 4; }
+}  // namespace
+
+int launch_pack_rows(int mode, const void* X, int64_t ldx, int64_t R, int64_t K, void* P, void* Plo,
+                     int64_t Rp, int64_t Kp, hipStream_t s)
+{
+    if (R > Rp || K > Kp || Kp % 8 != 0 || Rp > INT32_MAX || Kp > INT32_MAX) return TGEMM_INTERNAL;
+    // groups of 8 k are numbered in 32 bits, including the grid-stride overshoot
+    const int64_t groups = Rp * (Kp / 8);
+    if (groups >= ((int64_t)1 << 32) - 65536 * 256) return TGEMM_NOT_SUPPORTED;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 255) / 256, 65536));
+    const int vec = pack_rows_vec(X, ldx, mode_elem_bytes(mode));
+    switch (mode) {
+        case MODE_F32: pack_rows_mode<MODE_F32>(X, ldx, (int)R, (int)K, P, Plo, (int)Rp, (int)Kp, vec, grid, s); break;
+        case MODE_X3: pack_rows_mode<MODE_X3>(X, ldx, (int)R, (int)K, P, Plo, (int)Rp, (int)Kp, vec, grid, s); break;
+        case MODE_BF16: pack_rows_mode<MODE_BF16>(X, ldx, (int)R, (int)K, P, Plo, (int)Rp, (int)Kp, vec, grid, s); break;
+        case MODE_FP8: pack_rows_mode<MODE_FP8>(X, ldx, (int)R, (int)K, P, Plo, (int)Rp, (int)Kp, vec, grid, s); break;
+        default: return TGEMM_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+}
+
+int launch_pack_cols(int mode, const void* X, int64_t ldx, int64_t K, int64_t N, void* P, void* Plo,
+                     int64_t Np, int64_t Kp, hipStream_t s)
+{
+    if (N > Np || K > Kp || Np % 64 != 0 || Kp % 64 != 0 || Np > INT32_MAX || Kp > INT32_MAX)
+        return TGEMM_INTERNAL;
+    if (Np / 64 > 0x7FFFFFFF || Kp / 64 > 65535) return TGEMM_NOT_SUPPORTED;
+    const int vec = pack_cols_vec(X, ldx, mode_elem_bytes(mode));
+    switch (mode) {
+        case MODE_F32: pack_cols_mode<MODE_F32>(X, ldx, (int)K, (int)N, P, Plo, (int)Np, (int)Kp, vec, s); break;
+        case MODE_X3: pack_cols_mode<MODE_X3>(X, ldx, (int)K, (int)N, P, Plo, (int)Np, (int)Kp, vec, s); break;
+        case MODE_BF16: pack_cols_mode<MODE_BF16>(X, ldx, (int)K, (int)N, P, Plo, (int)Np, (int)Kp, vec, s); break;
+        case MODE_FP8: pack_cols_mode<MODE_FP8>(X, ldx, (int)K, (int)N, P, Plo, (int)Np, (int)Kp, vec, s); break;
+        default: return TGEMM_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+}
+
 // Pack A and B into `ws` and run packed schedule `pid` (index into kPacked).
 bool packed_k_ok(int64_t K, int dtype)
 {
@@ -200,38 +250,9 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     char* Bp = base + Mp * Kp * es * (p.mode == MODE_X3 ? 2 : 1);
     char* Blo = p.mode == MODE_X3 ? Bp + Np * Kp * es : nullptr;
 
-    const int64_t groups_a = Mp * (Kp / 8);
-    if (groups_a >= ((int64_t)1 << 32) - 65536 * 256) return TGEMM_NOT_SUPPORTED;
-    const int ves = p.dtype == TGEMM_FP8_E4M3 ? 1 : p.dtype == TGEMM_BF16 ? 2 : 4;
-    const int vec_a = pack_rows_vec(A, lda, ves), vec_b = pack_cols_vec(B, ldb, ves);
-    const unsigned ga = (unsigned)std::min<int64_t>((groups_a + 255) / 256, 65536);
-    const dim3 gb((unsigned)(Np / 64), (unsigned)(Kp / 64));
-    switch (p.mode) {
-        case MODE_F32:
-            hipLaunchKernelGGL(pack_rows_kernel<MODE_F32>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
-                               (int)K, Ap, nullptr, (int)Mp, (int)Kp, vec_a);
-            hipLaunchKernelGGL(pack_cols_kernel<MODE_F32>, gb, dim3(256), 0, s, B, ldb, (int)K, (int)N,
-                               Bp, nullptr, (int)Np, (int)Kp, vec_b);
-            break;
-        case MODE_X3:
-            hipLaunchKernelGGL(pack_rows_kernel<MODE_X3>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
-                               (int)K, Ap, Alo, (int)Mp, (int)Kp, vec_a);
-            hipLaunchKernelGGL(pack_cols_kernel<MODE_X3>, gb, dim3(256), 0, s, B, ldb, (int)K, (int)N,
-                               Bp, Blo, (int)Np, (int)Kp, vec_b);
-            break;
-        case MODE_BF16:
-            hipLaunchKernelGGL(pack_rows_kernel<MODE_BF16>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
-                               (int)K, Ap, nullptr, (int)Mp, (int)Kp, vec_a);
-            hipLaunchKernelGGL(pack_cols_kernel<MODE_BF16>, gb, dim3(256), 0, s, B, ldb, (int)K,
-                               (int)N, Bp, nullptr, (int)Np, (int)Kp, vec_b);
-            break;
-        default:
-            hipLaunchKernelGGL(pack_rows_kernel<MODE_FP8>, dim3(ga), dim3(256), 0, s, A, lda, (int)M,
-                               (int)K, Ap, nullptr, (int)Mp, (int)Kp, vec_a);
-            hipLaunchKernelGGL(pack_cols_kernel<MODE_FP8>, gb, dim3(256), 0, s, B, ldb, (int)K, (int)N,
-                               Bp, nullptr, (int)Np, (int)Kp, vec_b);
-            break;
-    }
+    int rc = launch_pack_rows(p.mode, A, lda, M, K, Ap, Alo, Mp, Kp, s);
+    if (rc == TGEMM_SUCCESS) rc = launch_pack_cols(p.mode, B, ldb, K, N, Bp, Blo, Np, Kp, s);
+    if (rc != TGEMM_SUCCESS) return rc;
     PackedArgs a;
     a.A = Ap;
     a.Alo = Alo;

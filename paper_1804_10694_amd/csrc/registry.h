@@ -38,6 +38,20 @@ size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype);
 bool packed_k_ok(int64_t K, int dtype);
 void packed_shutdown();
 void packed_release(hipStream_t s);  // frees the workspace of one stream
+// Per (device, stream) packing workspace of at least `bytes`, grown on demand
+// (never under stream capture: TGEMM_CAPTURE_UNPLANNED).
+int packed_workspace(hipStream_t s, size_t bytes, void** out);
+// Packing passes of one operand form (MODE_*).  pack rows: R x K rows of X
+// (row stride ldx) into Rp x Kp K-contiguous rows of P (and the low bf16
+// halves into Plo for MODE_X3), zero past R and K.  pack cols: the K x N
+// matrix X (row stride ldx) transposed into Np x Kp rows, zero past N and K.
+// Kp is a multiple of 8 (of 64 for pack cols), Np of 64.
+int launch_pack_rows(int mode, const void* X, int64_t ldx, int64_t R, int64_t K, void* P, void* Plo,
+                     int64_t Rp, int64_t Kp, hipStream_t s);
+int launch_pack_cols(int mode, const void* X, int64_t ldx, int64_t K, int64_t N, void* P, void* Plo,
+                     int64_t Np, int64_t Kp, hipStream_t s);
+constexpr int kPackRows = 256;  // packed row counts of the gemm path are multiples of this
+constexpr int kPackK = 128;     // packed K of the gemm path is a multiple of this (elements)
 // Position of a schedule id inside packed_schedules(), or -1.
 int packed_index(int id);
 

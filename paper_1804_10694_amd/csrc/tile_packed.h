@@ -473,11 +473,40 @@ __device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int 
     return a.sA[ia] * a.sB[ib];
 }
 
-// One BM x BN macro-tile at (m0, n0) of the packed problem `a`; `lds` holds
-// CF::LDS_BYTES.  The packed rows of A and B^T must extend to m0 + BM and
-// n0 + BN, and K to a multiple of BK, with zeros beyond K.
+// A-side panel loads over packed rows of A (a.A, and a.Alo for x3): the
+// default operand source of packed_tile.
 template <class CF>
-__device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds)
+struct PackedRowsA {
+    struct Geom {};
+    __amdgpu_buffer_rsrc_t r, rl;
+    int lane_off, row_bytes, wave;
+
+    __device__ __forceinline__ void init(const PackedArgs& a, int m0, int lane, int wave_, const Geom&)
+    {
+        wave = wave_;
+        row_bytes = a.Kp * CF::ES;
+        r = make_rsrc(a.A + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
+        rl = r;
+        if (CF::MODE == MODE_X3) rl = make_rsrc(a.Alo + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
+        lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
+    }
+
+    __device__ __forceinline__ void issue(int panel, char* stage) const
+    {
+        const int kb = panel * CF::BK * CF::ES;
+        load_panel<CF::UK, CF::A_INSTR>(r, lane_off, row_bytes, kb, stage, wave);
+        if (CF::MODE == MODE_X3)
+            load_panel<CF::UK, CF::A_INSTR>(rl, lane_off, row_bytes, kb, stage + CF::LDS_A, wave);
+    }
+};
+
+// One BM x BN macro-tile at (m0, n0) of the packed problem `a`; `lds` holds
+// CF::LDS_BYTES.  The packed rows of B^T must extend to n0 + BN, and K to a
+// multiple of BK, with zeros beyond K; AL loads the A panels (by default from
+// packed rows of A, which must extend to m0 + BM likewise).
+template <class CF, class AL = PackedRowsA<CF>>
+__device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds,
+                                            const typename AL::Geom& geom = typename AL::Geom())
 {
     const int t = threadIdx.x, lane = t & 63;
     // the wave index is uniform; readfirstlane lets the compiler keep it (and the
@@ -485,14 +514,12 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm0 = (wave / CF::WGN) * CF::WTM, wn0 = (wave % CF::WGN) * CF::WTN;
     const int row_bytes = a.Kp * CF::ES;
-    const __amdgpu_buffer_rsrc_t rA = make_rsrc(a.A + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
     const __amdgpu_buffer_rsrc_t rB = make_rsrc(a.B + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
-    __amdgpu_buffer_rsrc_t rAl = rA, rBl = rB;
-    if (CF::MODE == MODE_X3) {
-        rAl = make_rsrc(a.Alo + (int64_t)m0 * row_bytes, CF::BM * row_bytes);
-        rBl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
-    }
+    __amdgpu_buffer_rsrc_t rBl = rB;
+    if (CF::MODE == MODE_X3) rBl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
     const int lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
+    AL al;
+    al.init(a, m0, lane, wave, geom);
     const bool scaled = (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA;
 
     f32x16 acc[CF::TM][CF::TN];
@@ -506,9 +533,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     const int npanel = (a.K + CF::BK - 1) / CF::BK;
     auto issue = [&](int panel, char* stage) {
         const int kb = panel * CF::BK * CF::ES;
-        load_panel<CF::UK, CF::A_INSTR>(rA, lane_off, row_bytes, kb, stage, wave);
-        if (CF::MODE == MODE_X3)
-            load_panel<CF::UK, CF::A_INSTR>(rAl, lane_off, row_bytes, kb, stage + CF::LDS_A, wave);
+        al.issue(panel, stage);
         char* sb = stage + CF::NARR * CF::LDS_A;
         load_panel<CF::UK, CF::B_INSTR>(rB, lane_off, row_bytes, kb, sb, wave);
         if (CF::MODE == MODE_X3)

@@ -39,6 +39,8 @@ lib.tgemm_quantize_tiles.argtypes = [_i64, _i64, _p, _i64, _p, _i64, _p, _i32, _
 lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32, _pp,
                               _pi64, _i32, _p]
 lib.tgemm_conv3x3.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p]
+lib.tgemm_conv3x3_path.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _i32, _p]
+lib.tgemm_conv3x3_packed_shape.argtypes = [_i32, _i32, _p, _p, _p, _p]
 lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
                                          _pf32, _pp, _pi64, _i32, _i32, _i32, _p]
 lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
@@ -232,10 +234,26 @@ def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream
     return {"threshold": thr.value, "large": large.value}
 
 
-def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+CONV_AUTO, CONV_DIRECT, CONV_PACKED = 0, 1, 2
+
+
+def conv3x3_packed_shapes(dtype="f32"):
+    """(bm, bn, bk, stages) of each packed conv tile shape of `dtype`
+    (tgemm_conv3x3_packed_shape)."""
+    out = []
+    while True:
+        v = [ctypes.c_int32() for _ in range(4)]
+        if lib.tgemm_conv3x3_packed_shape(_dtype_code(dtype), len(out), *[ctypes.byref(x) for x in v]) != 0:
+            return out
+        out.append(tuple(x.value for x in v))
+
+
+def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None, path="auto", shape=0):
     """3x3 same-padding convolution as an implicit gemm (tgemm_conv3x3):
     Y = alpha * conv(X, Wt) + beta * Y, with X (batch, H, W, Cin), Wt (3, 3, Cin, Cout)
-    and Y (batch, H, W, Cout) contiguous float32 device tensors."""
+    and Y (batch, H, W, Cout) contiguous float32 device tensors.  path "auto" (the
+    library's choice), "direct", or "packed" with tile shape index `shape`
+    (tgemm_conv3x3_path)."""
     import torch
     for name, t in (("X", X), ("Wt", Wt), ("Y", Y)):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
@@ -244,8 +262,17 @@ def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None):
     nb, H, W, cin = X.shape
     if tuple(Wt.shape[:3]) != (3, 3, cin) or tuple(Y.shape) != (nb, H, W, Wt.shape[3]):
         raise ValueError("shapes must be X (b, H, W, Cin), Wt (3, 3, Cin, Cout), Y (b, H, W, Cout)")
-    _check(lib.tgemm_conv3x3(nb, H, W, cin, Wt.shape[3], alpha, X.data_ptr(), Wt.data_ptr(), beta,
-                             Y.data_ptr(), _dtype_code(dtype), _stream_handle(stream)), "tgemm_conv3x3")
+    if path == "auto":
+        code = CONV_AUTO
+    elif path == "direct":
+        code = CONV_DIRECT
+    elif path == "packed":
+        code = CONV_PACKED + int(shape)
+    else:
+        raise ValueError(f"unknown conv path {path!r}")
+    _check(lib.tgemm_conv3x3_path(nb, H, W, cin, Wt.shape[3], alpha, X.data_ptr(), Wt.data_ptr(), beta,
+                                  Y.data_ptr(), _dtype_code(dtype), code, _stream_handle(stream)),
+           "tgemm_conv3x3_path")
 
 
 def set_policy(policy):

@@ -143,3 +143,19 @@ def test_select_schedule_serves_dtype(tg):
 def test_schedule_keys_are_unique(tg):
     keys = [tg.schedule_key(i) for i in range(tg.schedule_count())]
     assert len(keys) == len(set(keys))
+
+
+def test_conv_packed_shapes_and_path_validation(tg):
+    # tile shapes of the packed 3x3 convolution kernel: host table, no HIP call
+    for dt in ("f32", "x3"):
+        shapes = tg.conv3x3_packed_shapes(dt)
+        assert len(shapes) >= 2 and len(set(shapes)) == len(shapes)
+        for bm, bn, bk, st in shapes:
+            assert bm in (128, 256) and bn in (128, 256) and 128 % bk == 0 and st >= 2
+    assert tg.conv3x3_packed_shapes("bf16") == []
+    # an unknown kernel choice is refused before any HIP call
+    args = (1, 4, 4, 8, 8, 1.0, FAKE, FAKE, 0.0, FAKE, 0)
+    assert tg.lib.tgemm_conv3x3_path(*args, 99 - 100, None) == 1
+    assert tg.lib.tgemm_conv3x3_path(*args, 2 + len(tg.conv3x3_packed_shapes("f32")), None) == 1
+    # empty layers are no-ops on every path
+    assert tg.lib.tgemm_conv3x3_path(0, 4, 4, 8, 8, 1.0, None, None, 0.0, None, 0, 2, None) == 0

@@ -36,34 +36,58 @@ def _inputs(nb, H, W, cin, cout, seed, integer):
     return X, Wt, Y0
 
 
-def _run(tg, X, Wt, Y0, alpha, beta, dtype):
+def _run(tg, X, Wt, Y0, alpha, beta, dtype, path="auto", shape=0):
     Yd = Y0.clone().to(DEV)
-    tg.conv3x3(X.to(DEV), Wt.to(DEV), Yd, alpha, beta, dtype)
+    tg.conv3x3(X.to(DEV), Wt.to(DEV), Yd, alpha, beta, dtype, path=path, shape=shape)
     torch.cuda.synchronize()
     return Yd.cpu()
 
 
-# ragged pixel counts, both tile sizes, Cout with and without 16-byte filter rows
+# every kernel: the direct one and each packed tile shape (the host table is fixed, so the
+# count is known without a GPU)
+KERNELS = [("direct", 0)] + [("packed", i) for i in range(4)]
+
+# ragged pixel counts, both direct tile sizes, packed tiles over one and several K panels
+# (Cin 8: 72 = 9 * 8 taps, not a panel multiple), Cout with and without 16-byte filter rows
+# and across several 128- and 256-column tiles
 SHAPES = [(2, 5, 7, 8, 12), (3, 9, 11, 16, 13), (1, 16, 16, 64, 64), (2, 17, 19, 24, 130),
-          (4, 24, 24, 32, 200)]
+          (4, 24, 24, 32, 200), (1, 20, 23, 16, 300)]
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=lambda k: f"{k[0]}{k[1]}")
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_integer_inputs_bit_exact(tg, dtype, shape):
+def test_integer_inputs_bit_exact(tg, dtype, shape, kernel):
+    print(f"conv {dtype} {shape} {kernel}", flush=True)
     X, Wt, Y0 = _inputs(*shape, seed=sum(shape), integer=True)
     ref = OC.conv3x3(X, Wt, Y0, 1.5, 0.5)
-    got = _run(tg, X, Wt, Y0, 1.5, 0.5, dtype)
-    np.testing.assert_array_equal(got.numpy().astype(np.float64), ref, err_msg=f"{dtype} {shape}")
+    got = _run(tg, X, Wt, Y0, 1.5, 0.5, dtype, *kernel)
+    np.testing.assert_array_equal(got.numpy().astype(np.float64), ref, err_msg=f"{dtype} {shape} {kernel}")
 
 
-@pytest.mark.parametrize("shape", [(2, 13, 11, 32, 48), (1, 28, 28, 64, 96)])
+def test_kernel_list_matches_library(tg):
+    for dt in ("f32", "x3"):
+        assert len(tg.conv3x3_packed_shapes(dt)) == len(KERNELS) - 1
+
+
+def test_f32_four_channel_input(tg):
+    # Cin = 4: one 16-byte unit per tap, K = 36 below one panel
+    X, Wt, Y0 = _inputs(3, 7, 9, 4, 24, seed=75, integer=True)
+    ref = OC.conv3x3(X, Wt, Y0, 1.0, -1.0)
+    for kernel in KERNELS:
+        got = _run(tg, X, Wt, Y0, 1.0, -1.0, "f32", *kernel)
+        np.testing.assert_array_equal(got.numpy().astype(np.float64), ref, err_msg=str(kernel))
+
+
+@pytest.mark.parametrize("shape", [(2, 13, 11, 32, 48), (1, 28, 28, 64, 96), (1, 9, 10, 512, 40)])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_uniform_inputs_within_tolerance(tg, dtype, shape):
+@pytest.mark.parametrize("path", ["direct", "packed"])
+def test_uniform_inputs_within_tolerance(tg, dtype, shape, path):
+    print(f"conv {dtype} {shape} {path}", flush=True)
     X, Wt, Y0 = _inputs(*shape, seed=7 + sum(shape), integer=False)
     ref = OC.conv3x3(X, Wt, Y0, 1.0, 1.0)
-    err = oracle.normwise_error(_run(tg, X, Wt, Y0, 1.0, 1.0, dtype).numpy(), ref)
-    print(f"{dtype} {shape} normwise error {err:.3e}")
+    err = oracle.normwise_error(_run(tg, X, Wt, Y0, 1.0, 1.0, dtype, path).numpy(), ref)
+    print(f"{dtype} {shape} {path} normwise error {err:.3e}")
     assert err <= 1e-5
 
 
@@ -77,19 +101,21 @@ def test_same_result_as_explicit_im2col_gemm(tg):
     C = Y0.clone().reshape(-1, cout).to(DEV)
     tg.gemm(cols.reshape(-1, 9 * cin).contiguous().to(DEV), Wt.reshape(9 * cin, cout).to(DEV), C, 1.0, 0.5,
             "f32")
-    got = _run(tg, X, Wt, Y0, 1.0, 0.5, "f32")
-    torch.cuda.synchronize()
-    assert torch.equal(got.reshape(-1, cout), C.cpu())
+    for kernel in KERNELS:
+        got = _run(tg, X, Wt, Y0, 1.0, 0.5, "f32", *kernel)
+        assert torch.equal(got.reshape(-1, cout), C.cpu()), kernel
 
 
 def test_degenerate_cases(tg):
     X, Wt, Y0 = _inputs(2, 6, 5, 8, 16, seed=71, integer=True)
-    # alpha == 0: Y = beta * Y, X and Wt not read (NaN there)
-    nanX = torch.full_like(X, float("nan"))
-    np.testing.assert_array_equal(_run(tg, nanX, Wt, Y0, 0.0, 0.5, "f32").numpy(), (0.5 * Y0).numpy())
-    # beta == 0 does not read Y (NaN there)
-    got = _run(tg, X, Wt, torch.full_like(Y0, float("nan")), 1.0, 0.0, "x3")
-    np.testing.assert_array_equal(got.numpy().astype(np.float64), OC.conv3x3(X, Wt))
+    for kernel in KERNELS[:2]:
+        # alpha == 0: Y = beta * Y, X and Wt not read (NaN there)
+        nanX = torch.full_like(X, float("nan"))
+        np.testing.assert_array_equal(_run(tg, nanX, Wt, Y0, 0.0, 0.5, "f32", *kernel).numpy(),
+                                      (0.5 * Y0).numpy())
+        # beta == 0 does not read Y (NaN there)
+        got = _run(tg, X, Wt, torch.full_like(Y0, float("nan")), 1.0, 0.0, "x3", *kernel)
+        np.testing.assert_array_equal(got.numpy().astype(np.float64), OC.conv3x3(X, Wt))
     # Cin not a multiple of the 16-byte unit is refused; empty batch is a no-op
     Xo, Wo, Yo = _inputs(1, 4, 4, 6, 8, seed=72, integer=True)
     with pytest.raises(tg.TgemmError):
@@ -99,12 +125,13 @@ def test_degenerate_cases(tg):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_full_size_layer_sampled(tg, dtype):
-    # a 3x3 layer at the benchmark's size (batch 32, 56 x 56, 128 -> 128 channels), sampled
+@pytest.mark.parametrize("path", ["auto", "direct"])
+def test_full_size_layer_sampled(tg, dtype, path):
+    # a 3x3 layer at the benchmark's size (batch 32, 56 x 56, 256 -> 256 channels), sampled
     # output pixels against the oracle, including image borders and corners
-    nb, H, W, cin, cout = 32, 56, 56, 128, 128
+    nb, H, W, cin, cout = 32, 56, 56, 256, 256
     X, Wt, Y0 = _inputs(nb, H, W, cin, cout, seed=73, integer=False)
-    got = _run(tg, X, Wt, Y0, 1.0, 1.0, dtype).reshape(-1, cout)
+    got = _run(tg, X, Wt, Y0, 1.0, 1.0, dtype, path).reshape(-1, cout)
     rng = np.random.default_rng(74)
     pix = np.concatenate([rng.choice(nb * H * W, 400, replace=False),
                           [0, W - 1, (H - 1) * W, H * W - 1, nb * H * W - 1]])
@@ -112,3 +139,35 @@ def test_full_size_layer_sampled(tg, dtype):
     err = oracle.normwise_error(got[torch.from_numpy(pix)].numpy(), ref)
     print(f"{dtype} full-size layer sampled normwise error {err:.3e}")
     assert err <= 1e-5
+
+
+def test_packed_path_refuses_inputs_beyond_its_reach(tg):
+    # X of 2^31 bytes or more is beyond the packed kernel's 32-bit buffer offsets: the packed
+    # path is refused before any launch (pointers are never read), the direct one takes it
+    X = torch.zeros(16, device=DEV)
+    rc = tg.lib.tgemm_conv3x3_path(1, 1 << 15, 1 << 12, 4, 8, 1.0, X.data_ptr(), X.data_ptr(), 0.0,
+                                   X.data_ptr(), 0, tg.CONV_PACKED, None)
+    assert rc == 2
+
+
+def test_graph_replay(tg):
+    # the packed path (filter packing, x3 input split and the conv kernel) captured in a HIP
+    # graph after a warm-up call has sized its workspace; every replay matches the eager result
+    X, Wt, Y0 = _inputs(2, 12, 13, 16, 40, seed=76, integer=True)
+    Xd, Wd = X.to(DEV), Wt.to(DEV)
+    for dt in ("f32", "x3"):
+        eager = Y0.clone().to(DEV)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            tg.conv3x3(Xd, Wd, eager, 1.0, 0.5, dt, stream=s)
+        torch.cuda.synchronize()
+        Yg = Y0.clone().to(DEV)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            tg.conv3x3(Xd, Wd, Yg, 1.0, 0.5, dt, stream=s)
+        for _ in range(3):
+            Yg.copy_(Y0.to(DEV))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(Yg, eager), dt
