@@ -38,6 +38,7 @@
 #include "kargs.h"
 #include "registry.h"
 #include "tile_f32x3.h"
+#include "tile_inplace.h"
 #include "tile_packed.h"
 
 namespace tg {
@@ -65,6 +66,7 @@ struct GroupDesc {
     char* Blo;
     int Mp, Np, Kp;
     int vec_a, vec_b;  // the packing may use vector loads on A / B
+    int ip_vec;        // in-place class: 16-byte loads (else 4-byte)
     int row_units;     // packing work units of A (256 groups of 8 k each); B^T units follow
 };
 
@@ -95,6 +97,25 @@ template <int MODE>
 using GroupPacked = PCfg<MODE, 256, 256, 32, 2, 4, 2>;
 constexpr int kPackedTile = 256;
 constexpr int kPackedKPad = 32;  // packed K is a multiple of this (the panel depth)
+
+// The in-place class's configuration: 64 x 64 macro-tiles of 4 waves whose K
+// panels go straight from the caller's A and B into LDS (tile_inplace.h),
+// 16-deep panels in two 8 KB stages, so that eight workgroups fit per CU: with
+// K of a few hundred, workgroups in flight hide the panel latency better than
+// deeper pipelines (measured on MI355X over 512 problems in [16, 2048]^3:
+// 16-deep panels in 2 stages, 8 workgroups per CU, beat 3 stages with 6, 4
+// with 5 and 32-deep panels with 3 to 5 by 5-18%).
+// x3 stops at 6 per CU: its operand split needs more than the 64 registers a
+// wave may hold at 8.
+template <int MODE>
+using GroupInplace = ICfg<MODE, 64, 64, 16, 2, 2, 2>;
+template <int MODE>
+constexpr int kInplaceCap = (MODE == MODE_F32) ? 8 : 6;
+template <int MODE>
+constexpr int kInplaceOcc = (160 * 1024) / GroupInplace<MODE>::LDS_BYTES > kInplaceCap<MODE>
+                                ? kInplaceCap<MODE>
+                                : (160 * 1024) / GroupInplace<MODE>::LDS_BYTES;
+constexpr int kInplaceTile = 64;
 
 template <class CF>
 __device__ __forceinline__ void run_tile(const GemmArgs& a, int local, char* lds)
@@ -166,6 +187,8 @@ __global__ void __launch_bounds__(GroupPacked<MODE>::NT, 1)
         a.ldc = g.ldc;
         a.lds_a = 0;
         a.lds_b = 0;
+        a.lda = 0;
+        a.ldb = 0;
         a.M = g.M;
         a.N = g.N;
         a.K = g.K;
@@ -178,6 +201,46 @@ __global__ void __launch_bounds__(GroupPacked<MODE>::NT, 1)
         a.xcd_remap = 0;
         const TileCoord tc = map_tile(pl.y, g.tiles_m, g.tiles_n, 8, 0);
         packed_tile<CF>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds);
+        __syncthreads();  // the next tile's loads reuse the LDS
+    }
+}
+
+// Persistent kernel of the in-place class.
+template <int MODE>
+__global__ void __launch_bounds__(GroupInplace<MODE>::NT, kInplaceOcc<MODE>)
+    grouped_inplace_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, int total)
+{
+    using CF = GroupInplace<MODE>;
+    __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int2 pl = map[t];  // (problem, tile within it)
+        const GroupDesc& g = desc[pl.x];
+        PackedArgs a;
+        a.A = static_cast<const char*>(g.A);
+        a.Alo = nullptr;
+        a.B = static_cast<const char*>(g.B);
+        a.Blo = nullptr;
+        a.C = g.C;
+        a.sA = nullptr;
+        a.sB = nullptr;
+        a.ldc = g.ldc;
+        a.lds_a = 0;
+        a.lds_b = 0;
+        a.lda = g.lda;
+        a.ldb = g.ldb;
+        a.M = g.M;
+        a.N = g.N;
+        a.K = g.K;
+        a.Kp = 0;
+        a.alpha = g.alpha;
+        a.beta = g.beta;
+        a.tiles_m = g.tiles_m;
+        a.tiles_n = g.tiles_n;
+        a.group_m = 8;
+        a.xcd_remap = 0;
+        const TileCoord tc = map_tile(pl.y, g.tiles_m, g.tiles_n, 8, 0);
+        if (g.ip_vec) inplace_tile<CF, true>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds);
+        else inplace_tile<CF, false>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds);
         __syncthreads();  // the next tile's loads reuse the LDS
     }
 }
@@ -246,7 +309,7 @@ struct Plan {
     int dtype = 0;
     int device = -1;
     GroupDesc* d_desc = nullptr;
-    Space pack, packed, direct;  // packing pass, packed class tiles, direct class tiles
+    Space pack, packed, inplace, direct;  // packing pass, packed, in-place and direct class tiles
     bool mixed = false;          // the direct class has 128 x 128 tiles
     char* ws = nullptr;          // packed operands
 };
@@ -290,6 +353,16 @@ constexpr int kLarge[] = {256, 512, 1024, kNever};
 
 bool reaches(const GroupDesc& g, int t) { return g.M >= t && g.N >= t; }
 
+// Whether a direct-class problem with 64 x 64 tiles can take the in-place
+// tiles: a tile's rows of A and a panel's rows of B within the 32-bit reach of
+// a buffer offset.
+bool inplace_ok(const GroupDesc& g)
+{
+    return (int64_t)kInplaceTile * g.lda * 4 <= INT32_MAX &&
+           (int64_t)GroupInplace<MODE_F32>::BK * g.ldb * 4 <= INT32_MAX &&
+           (int64_t)GroupInplace<MODE_X3>::BK * g.ldb * 4 <= INT32_MAX;
+}
+
 // Tuned plan shapes by problem-set dimensions (pointers, alpha and beta left out).
 std::map<uint64_t, Shape> g_tuned_shape;
 
@@ -329,9 +402,11 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
                const int64_t* ldb, const float* beta, float* const* C, const int64_t* ldc, int dtype,
                Shape shape, Plan* plan)
 {
-    // packed problems first, then the direct ones; heaviest tiles first in each
+    // packed problems first, then the in-place ones, then the direct ones;
+    // heaviest tiles first in each class
+    enum { kDirect = 0, kPacked = 1, kInplace = 2 };
     std::vector<GroupDesc> descs;
-    std::vector<char> is_packed;
+    std::vector<char> cls;
     for (int64_t p = 0; p < count; ++p) {
         if (M[p] == 0 || N[p] == 0) continue;
         GroupDesc g;
@@ -360,29 +435,36 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         }
         g.tiles_m = (int)((M[p] + t - 1) / t);
         g.tiles_n = (int)((N[p] + t - 1) / t);
+        char c = pk ? kPacked : kDirect;
+        if (!pk && !g.scale_only && g.cfg < 2 && inplace_ok(g)) {
+            c = kInplace;
+            // 16-byte units need aligned rows and no unit across the end of a row
+            g.ip_vec = (g.cfg == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
+        }
         descs.push_back(g);
-        is_packed.push_back(pk ? 1 : 0);
+        cls.push_back(c);
     }
     std::vector<size_t> order(descs.size());
     std::iota(order.begin(), order.end(), 0);
     auto work = [&](size_t i) {
         const GroupDesc& g = descs[i];
         if (g.scale_only) return 0.0;
-        const double t = is_packed[i] ? kPackedTile : kGroupTile[g.cfg];
+        const double t = cls[i] == kPacked ? kPackedTile : cls[i] == kInplace ? kInplaceTile : kGroupTile[g.cfg];
         return t * t * g.K;
     };
+    auto rank = [&](size_t i) { return cls[i] == kPacked ? 0 : cls[i] == kInplace ? 1 : 2; };
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-        if (is_packed[x] != is_packed[y]) return is_packed[x] > is_packed[y];
+        if (rank(x) != rank(y)) return rank(x) < rank(y);
         return work(x) > work(y);
     });
     std::vector<GroupDesc> sorted;
-    std::vector<char> sorted_packed;
+    std::vector<char> sorted_cls;
     for (size_t i : order) {
         sorted.push_back(descs[i]);
-        sorted_packed.push_back(is_packed[i]);
+        sorted_cls.push_back(cls[i]);
     }
     descs.swap(sorted);
-    is_packed.swap(sorted_packed);
+    cls.swap(sorted_cls);
     plan->dtype = dtype;
     (void)hipGetDevice(&plan->device);
     if (descs.empty()) return TGEMM_SUCCESS;
@@ -392,11 +474,17 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     const int64_t arrays = dtype == TGEMM_F32_BF16X3 ? 2 : 1, esz = 4 / arrays;
     int64_t off = 0;
     std::vector<int64_t> offs(descs.size(), 0);
-    std::vector<int> pack_units, packed_tiles, direct_tiles, pack_owner, packed_owner, direct_owner;
+    std::vector<int> pack_units, packed_tiles, inplace_tiles, direct_tiles;
+    std::vector<int> pack_owner, packed_owner, inplace_owner, direct_owner;
     for (size_t i = 0; i < descs.size(); ++i) {
         GroupDesc& g = descs[i];
         const int tiles = g.tiles_m * g.tiles_n;
-        if (!is_packed[i]) {
+        if (cls[i] == kInplace) {
+            inplace_tiles.push_back(tiles);
+            inplace_owner.push_back((int)i);
+            continue;
+        }
+        if (cls[i] == kDirect) {
             direct_tiles.push_back(tiles);
             direct_owner.push_back((int)i);
             continue;
@@ -420,7 +508,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     if (off > 0) {
         if (hipMalloc(&plan->ws, (size_t)off) != hipSuccess) return TGEMM_ALLOC_FAILED;
         for (size_t i = 0; i < descs.size(); ++i) {
-            if (!is_packed[i]) continue;
+            if (cls[i] != kPacked) continue;
             GroupDesc& g = descs[i];
             char* base = plan->ws + offs[i];
             const int64_t a_bytes = (int64_t)g.Mp * g.Kp * esz, b_bytes = (int64_t)g.Np * g.Kp * esz;
@@ -433,6 +521,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     int rc;
     if ((rc = upload_map(pack_units, pack_owner, &plan->pack)) != TGEMM_SUCCESS) return rc;
     if ((rc = upload_map(packed_tiles, packed_owner, &plan->packed)) != TGEMM_SUCCESS) return rc;
+    if ((rc = upload_map(inplace_tiles, inplace_owner, &plan->inplace)) != TGEMM_SUCCESS) return rc;
     if ((rc = upload_map(direct_tiles, direct_owner, &plan->direct)) != TGEMM_SUCCESS) return rc;
     const bool f32 = dtype == TGEMM_F32;
     plan->pack.grid = resident_grid(f32 ? (const void*)&grouped_pack_kernel<MODE_F32>
@@ -440,8 +529,11 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     plan->packed.grid = resident_grid(f32 ? (const void*)&grouped_packed_kernel<MODE_F32>
                                           : (const void*)&grouped_packed_kernel<MODE_X3>,
                                       GroupPacked<MODE_F32>::NT, plan->packed.total);
+    plan->inplace.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32>
+                                           : (const void*)&grouped_inplace_kernel<MODE_X3>,
+                                       GroupInplace<MODE_F32>::NT, plan->inplace.total);
     for (size_t i = 0; i < descs.size(); ++i)
-        plan->mixed = plan->mixed || (!is_packed[i] && !descs[i].scale_only && descs[i].cfg >= 2);
+        plan->mixed = plan->mixed || (cls[i] == kDirect && !descs[i].scale_only && descs[i].cfg >= 2);
     const void* direct_fn =
         plan->mixed ? (f32 ? (const void*)&grouped_kernel<MODE_F32, true> : (const void*)&grouped_kernel<MODE_X3, true>)
                     : (f32 ? (const void*)&grouped_kernel<MODE_F32, false> : (const void*)&grouped_kernel<MODE_X3, false>);
@@ -456,7 +548,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
 
 void free_plan(Plan& p)
 {
-    for (Space* sp : {&p.pack, &p.packed, &p.direct}) {
+    for (Space* sp : {&p.pack, &p.packed, &p.inplace, &p.direct}) {
         if (sp->d_map) (void)hipFree(sp->d_map);
         sp->d_map = nullptr;
     }
@@ -475,6 +567,9 @@ void launch_modes(const Plan& p, hipStream_t s)
     if (p.packed.total > 0)
         hipLaunchKernelGGL(grouped_packed_kernel<MODE>, dim3(p.packed.grid), dim3(GroupPacked<MODE>::NT), 0,
                            s, p.d_desc, p.packed.d_map, p.packed.total);
+    if (p.inplace.total > 0)
+        hipLaunchKernelGGL(grouped_inplace_kernel<MODE>, dim3(p.inplace.grid), dim3(GroupInplace<MODE>::NT), 0,
+                           s, p.d_desc, p.inplace.d_map, p.inplace.total);
     if (p.direct.total > 0 && p.mixed)
         hipLaunchKernelGGL((grouped_kernel<MODE, true>), dim3(p.direct.grid), dim3(256), 0, s, p.d_desc,
                            p.direct.d_map, p.direct.total);

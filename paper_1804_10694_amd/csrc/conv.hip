@@ -113,6 +113,7 @@ template <class CF>
 struct ConvRowsA {
     using Geom = ConvGeom;
     static constexpr int NI = CF::A_INSTR, UK = CF::UK, KU = CF::KU;
+    static constexpr int LOADS = CF::NARR * NI;  // loads per wave per panel
     static constexpr int OOB = INT32_MIN;  // offset 2^31: beyond any resource here, reads zero
 
     __amdgpu_buffer_rsrc_t r, rl;

@@ -339,6 +339,7 @@ struct PackedArgs {
     const float* sA;
     const float* sB;
     int64_t ldc, lds_a, lds_b;
+    int64_t lda, ldb;  // in-place tiles: the caller's row strides (elements)
     int M, N, K, Kp;
     float alpha, beta;
     int tiles_m, tiles_n, group_m, xcd_remap;
@@ -436,21 +437,39 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
     }
 }
 
+// Operand policy of packed_tile over the packed LDS layout: the registers of
+// one MFMA group, their LDS reads and the MFMAs, and how many of each there
+// are (for interleaving).
+template <class CF>
+struct PackedOps {
+    using Ops = PkOps<CF>;
+    static constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
+    static constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
+    __device__ __forceinline__ static void load(const char* stage, Ops& o, int g, int wm0, int wn0, int lane)
+    {
+        pk_load<CF>(stage, o, g, wm0, wn0, lane);
+    }
+    __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN])
+    {
+        pk_compute<CF>(o, acc);
+    }
+};
+
 // MFMAs over one LDS stage.  Operand registers are double-buffered: the reads
 // of group g + 1 are issued before the MFMAs of group g, and the scheduler is
 // asked to interleave them, so LDS latency hides behind the matrix unit.
-template <class CF>
+template <class CF, class OP = PackedOps<CF>>
 __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
                                        int wn0, int lane)
 {
-    constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
-    constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
-    PkOps<CF> ops[2];
-    pk_load<CF>(stage, ops[0], 0, wm0, wn0, lane);
+    constexpr int NREAD = OP::NREAD;
+    constexpr int NMFMA = OP::NMFMA;
+    typename OP::Ops ops[2];
+    OP::load(stage, ops[0], 0, wm0, wn0, lane);
 #pragma unroll
     for (int g = 0; g < CF::NG; ++g) {
-        if (g + 1 < CF::NG) pk_load<CF>(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
-        pk_compute<CF>(ops[g & 1], acc);
+        if (g + 1 < CF::NG) OP::load(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
+        OP::compute(ops[g & 1], acc);
         if (g + 1 < CF::NG) {
             // one LDS read between consecutive MFMAs while both last
 #pragma unroll
@@ -478,6 +497,7 @@ __device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int 
 template <class CF>
 struct PackedRowsA {
     struct Geom {};
+    static constexpr int LOADS = CF::NARR * CF::A_INSTR;  // loads per wave per panel
     __amdgpu_buffer_rsrc_t r, rl;
     int lane_off, row_bytes, wave;
 
@@ -500,11 +520,41 @@ struct PackedRowsA {
     }
 };
 
-// One BM x BN macro-tile at (m0, n0) of the packed problem `a`; `lds` holds
-// CF::LDS_BYTES.  The packed rows of B^T must extend to n0 + BN, and K to a
-// multiple of BK, with zeros beyond K; AL loads the A panels (by default from
-// packed rows of A, which must extend to m0 + BM likewise).
-template <class CF, class AL = PackedRowsA<CF>>
+// B-side panel loads over packed rows of B^T (a.B, and a.Blo for x3): the
+// default operand source of packed_tile.  `stage` is the B part of an LDS stage.
+template <class CF>
+struct PackedRowsB {
+    static constexpr int LOADS = CF::NARR * CF::B_INSTR;
+    __amdgpu_buffer_rsrc_t r, rl;
+    int lane_off, row_bytes, wave;
+
+    __device__ __forceinline__ void init(const PackedArgs& a, int n0, int lane, int wave_)
+    {
+        wave = wave_;
+        row_bytes = a.Kp * CF::ES;
+        r = make_rsrc(a.B + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
+        rl = r;
+        if (CF::MODE == MODE_X3) rl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
+        lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
+    }
+
+    __device__ __forceinline__ void issue(int panel, char* stage) const
+    {
+        const int kb = panel * CF::BK * CF::ES;
+        load_panel<CF::UK, CF::B_INSTR>(r, lane_off, row_bytes, kb, stage, wave);
+        if (CF::MODE == MODE_X3)
+            load_panel<CF::UK, CF::B_INSTR>(rl, lane_off, row_bytes, kb, stage + CF::LDS_B, wave);
+    }
+};
+
+// One BM x BN macro-tile at (m0, n0) of problem `a`; `lds` holds
+// CF::LDS_BYTES.  AL and BL bring the A and B panels into an LDS stage (A
+// first, B at offset NARR * LDS_A), each issuing a fixed number of loads per
+// wave per panel (AL::LOADS + BL::LOADS in all); OP reads the MFMA operands
+// from a stage and runs the MFMAs.  By default both operands come from packed
+// rows (of A and of B^T), which must extend to m0 + BM and n0 + BN, and K to
+// a multiple of BK, with zeros beyond K.
+template <class CF, class AL = PackedRowsA<CF>, class BL = PackedRowsB<CF>, class OP = PackedOps<CF>>
 __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds,
                                             const typename AL::Geom& geom = typename AL::Geom())
 {
@@ -513,13 +563,10 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     // load offsets and LDS bases derived from it) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm0 = (wave / CF::WGN) * CF::WTM, wn0 = (wave % CF::WGN) * CF::WTN;
-    const int row_bytes = a.Kp * CF::ES;
-    const __amdgpu_buffer_rsrc_t rB = make_rsrc(a.B + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
-    __amdgpu_buffer_rsrc_t rBl = rB;
-    if (CF::MODE == MODE_X3) rBl = make_rsrc(a.Blo + (int64_t)n0 * row_bytes, CF::BN * row_bytes);
-    const int lane_off = (lane / CF::UK) * row_bytes + (((lane % CF::UK) ^ (lane / 16)) & (CF::UK - 1)) * 16;
     AL al;
     al.init(a, m0, lane, wave, geom);
+    BL bl;
+    bl.init(a, n0, lane, wave);
     const bool scaled = (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA;
 
     f32x16 acc[CF::TM][CF::TN];
@@ -532,16 +579,13 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
 
     const int npanel = (a.K + CF::BK - 1) / CF::BK;
     auto issue = [&](int panel, char* stage) {
-        const int kb = panel * CF::BK * CF::ES;
         al.issue(panel, stage);
-        char* sb = stage + CF::NARR * CF::LDS_A;
-        load_panel<CF::UK, CF::B_INSTR>(rB, lane_off, row_bytes, kb, sb, wave);
-        if (CF::MODE == MODE_X3)
-            load_panel<CF::UK, CF::B_INSTR>(rBl, lane_off, row_bytes, kb, sb + CF::LDS_B, wave);
+        bl.issue(panel, stage + CF::NARR * CF::LDS_A);
     };
 
     // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
-    constexpr int NS = CF::NS, L = CF::LOADS_PER_STAGE;
+    constexpr int NS = CF::NS, L = AL::LOADS + BL::LOADS;
+    static_assert((NS - 2) * L <= 63, "vmcnt holds at most 63");
     for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
     int kb_cur = 0;
     // new K scale block at panel s: keep acc divided by the current scale product
@@ -570,7 +614,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
             lds_barrier();
             if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
             rescale(s);
-            pk_mma<CF>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+            pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
         }
     } else {
         // Three or more stages: the next panel has landed before this one ends, so
@@ -580,14 +624,12 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         // panel s + 1 follows this wave's last LDS read of panel s, so the refill of
         // panel s's stage (issued after it, at the top of the next iteration) never
         // overtakes a read.
-        constexpr int NREAD = PkOps<CF>::AV * PkOps<CF>::NA * (CF::TM + CF::TN);
-        constexpr int NMFMA = CF::TM * CF::TN * (CF::MODE == MODE_X3 ? 3 : CF::MODE == MODE_F32 ? 4 : 1);
-        constexpr int NPAIR = NREAD < NMFMA ? NREAD : NMFMA;
-        PkOps<CF> ops[2];
+        constexpr int NPAIR = OP::NREAD < OP::NMFMA ? OP::NREAD : OP::NMFMA;
+        typename OP::Ops ops[2];
         if (NS - 2 < npanel) wait_vmcnt<(NS - 2) * L>();
         else wait_vmcnt<0>();
         lds_barrier();
-        pk_load<CF>(lds, ops[0], 0, wm0, wn0, lane);
+        OP::load(lds, ops[0], 0, wm0, wn0, lane);
         for (int s = 0; s < npanel; ++s) {
             if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
             rescale(s);
@@ -596,17 +638,17 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
             for (int g = 0; g < CF::NG; ++g) {
                 bool read = false;
                 if (g + 1 < CF::NG) {
-                    pk_load<CF>(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
+                    OP::load(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
                     read = true;
                 } else if (s + 1 < npanel) {
                     if (s + NS - 1 < npanel) wait_vmcnt<(NS - 2) * L>();
                     else wait_vmcnt<0>();
                     wait_lds_reads();
                     lds_barrier();
-                    pk_load<CF>(lds + ((s + 1) % NS) * CF::LDS_STAGE, ops[CF::NG & 1], 0, wm0, wn0, lane);
+                    OP::load(lds + ((s + 1) % NS) * CF::LDS_STAGE, ops[CF::NG & 1], 0, wm0, wn0, lane);
                     read = true;
                 }
-                pk_compute<CF>(ops[g & 1], acc);
+                OP::compute(ops[g & 1], acc);
                 if (read) {
 #pragma unroll
                     for (int k = 0; k < NPAIR; ++k) {

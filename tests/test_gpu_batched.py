@@ -100,6 +100,59 @@ def test_alpha_zero_and_padded_strides(tg, large):
         assert torch.isnan(views[p][:, host[p][2].shape[1]:]).all()    # canaries intact
 
 
+# in-place class (64 x 64 tiles, panels of 16).  16-byte loads: K and N multiples of 4 on
+# 16-byte aligned rows; K below, at and past one panel, ragged M and N, one-row and one-unit
+# problems.  4-byte loads: any K and N, rows at any 4-byte offset.
+INPLACE_DIMS = [(1, 4, 4), (65, 68, 20), (130, 132, 36), (64, 64, 64), (200, 100, 100),
+                (17, 260, 8), (129, 4, 516), (300, 300, 12), (3, 76, 1000)]
+INPLACE_DIMS_ODD = [(1, 1, 1), (5, 7, 3), (65, 67, 21), (131, 129, 37), (70, 3, 517), (64, 64, 17),
+                    (33, 250, 15), (250, 33, 31), (2, 130, 1001)]
+
+
+@pytest.mark.parametrize("pad", [4, 3], ids=["vec16", "vec4"])
+@pytest.mark.parametrize("dims", [INPLACE_DIMS, INPLACE_DIMS_ODD], ids=["aligned", "odd"])
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad):
+    # All problems take the in-place tiles (direct 64 x 64 class).  A and B sit in buffers
+    # `pad` (or pad + 4) columns wider than the matrices, the extra columns NaN: A past K
+    # (the row's tail) must read as zero, and B's columns past N only reach accumulator
+    # columns that are never stored.  C's canary columns must stay NaN.  Odd dimensions or
+    # a pad of 3 (rows off 16-byte alignment) take the 4-byte loads.
+    host = _problem_set(dims, 5400, integer=True)
+    As, Bs, Cs, views = [], [], [], []
+    for p, (A, B, C0) in enumerate(host):
+        pad = pad if p % 2 else pad + 4
+        Ab, _ = inputs.padded(A, pad)
+        Bb, _ = inputs.padded(B, pad)
+        Cb, _ = inputs.padded(C0, 3)
+        Ad, Bd, Cd = Ab.to(DEV), Bb.to(DEV), Cb.to(DEV)
+        As.append(Ad[:, :A.shape[1]])
+        Bs.append(Bd[:, :B.shape[1]])
+        Cs.append(Cd[:, :C0.shape[1]])
+        views.append(Cd)
+    alphas = [1.5 if p % 2 else 1.0 for p in range(len(host))]
+    betas = [0.5 if p % 3 else 0.0 for p in range(len(host))]
+    print(f"in-place {dtype} pad {pad}", flush=True)
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape={"threshold": NEVER, "large": NEVER})
+    torch.cuda.synchronize()
+    for p, h in enumerate(host):
+        ref = oracle.gemm(h[0], h[1], h[2], alphas[p], betas[p])
+        np.testing.assert_array_equal(Cs[p].cpu().numpy().astype(np.float64), ref,
+                                      err_msg=f"problem {p} {dims[p]}")
+        assert torch.isnan(views[p][:, h[2].shape[1]:]).all()
+
+
+@pytest.mark.parametrize("dims", [INPLACE_DIMS, INPLACE_DIMS_ODD], ids=["aligned", "odd"])
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_inplace_tiles_uniform_inputs(tg, dtype, dims):
+    host = _problem_set(dims, 5500)
+    alphas, betas = [1.0] * len(host), [1.0] * len(host)
+    got = _run_batched(tg, host, alphas, betas, dtype, {"threshold": NEVER, "large": NEVER})
+    for p, (h, g) in enumerate(zip(host, got)):
+        ref = oracle.gemm(h[0], h[1], h[2], 1.0, 1.0)
+        assert oracle.normwise_error(g.numpy(), ref) <= 1e-5, f"problem {p} {dims[p]}"
+
+
 @pytest.mark.parametrize("shape", [None, {"threshold": 96, "large": NEVER}], ids=["default", "direct"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_grouped_config_512_problems(tg, dtype, shape):
