@@ -27,7 +27,7 @@ the path on their own workloads:
     replayed from a HIP graph.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-extras]
+                       [--no-extras] [--extras-only]
 """
 import argparse
 import json
@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the extra rows (for profiling them) and print them as JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one plain 1 GiB device copy (reference for the HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -236,6 +238,9 @@ def main():
 
     dev = torch.device("cuda:0")
     tg.set_policy("default")
+    if args.extras_only:
+        print(json.dumps({"extra_rows": extra_rows(tg, inputs)}))
+        return
     sq = (8192, 8192, 8192)
     rg = (4097, 3001, 2053)
     host = {sq: inputs.gemm_inputs(*sq, seed=2), rg: inputs.gemm_inputs(*rg, seed=3)}
