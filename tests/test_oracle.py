@@ -422,3 +422,66 @@ def test_conv_pixel_subset_and_degenerate_scalars():
     nan = np.full_like(Y0, np.nan)
     assert np.isfinite(OC.conv3x3(X, Wt, nan, 1.0, 0.0)).all()
     np.testing.assert_array_equal(OC.conv3x3(X, Wt, Y0, 0.0, 0.5), 0.5 * Y0)
+
+
+# ---------------------------------------------------------------- back-to-back gemm oracle
+from oracle import gemm2 as G2  # noqa: E402
+
+
+def _int_chain(M, K, N1, N2, seed):
+    g = np.random.default_rng(seed)
+    return (g.integers(-4, 5, (M, K)).astype(np.float64), g.integers(-4, 5, (K, N1)).astype(np.float64),
+            g.integers(-4, 5, (N1, N2)).astype(np.float64), g.integers(-4, 5, (M, N2)).astype(np.float64))
+
+
+@pytest.mark.parametrize("relu", [False, True])
+def test_gemm2_brute_force_tiny(relu):
+    # every output element by explicit loops over both sums
+    A, B, D, E0 = _int_chain(3, 4, 5, 2, seed=81)
+    M, K = A.shape
+    N1, N2 = D.shape
+    ref = np.zeros((M, N2))
+    for i in range(M):
+        for j in range(N2):
+            s = 0.0
+            for h in range(N1):
+                t = 0.0
+                for k in range(K):
+                    t += A[i, k] * B[k, h]
+                if relu and t < 0:
+                    t = 0.0
+                s += t * D[h, j]
+            ref[i, j] = 2.0 * s - 1.0 * E0[i, j]
+    np.testing.assert_array_equal(G2.gemm2(A, B, D, E0, 2.0, -1.0, relu), ref)
+
+
+def test_gemm2_identity_second_factor_is_the_gemm():
+    # D = I without activation: E = alpha A B + beta E0, the gemm oracle's own loop
+    A, B, _, E0 = _int_chain(6, 7, 5, 5, seed=82)
+    np.testing.assert_array_equal(G2.gemm2(A, B, np.eye(5), E0, 1.5, 0.5), oracle.gemm(A, B, E0, 1.5, 0.5))
+
+
+def test_gemm2_is_relu_between_two_gemm_oracle_calls():
+    A, B, D, E0 = _int_chain(9, 8, 7, 6, seed=83)
+    T = oracle.gemm(A, B)
+    T[T < 0] = 0.0
+    np.testing.assert_array_equal(G2.gemm2(A, B, D, E0, 1.0, 0.5, relu=True), oracle.gemm(T, D, E0, 1.0, 0.5))
+
+
+def test_gemm2_closed_forms():
+    A, B, D, E0 = _int_chain(5, 4, 3, 6, seed=84)
+    # A B <= 0 everywhere (A >= 0, B <= 0): ReLU zeroes T, E = beta E0
+    Ap, Bn = np.abs(A), -np.abs(B)
+    np.testing.assert_array_equal(G2.gemm2(Ap, Bn, D, E0, 3.0, 0.5, relu=True), 0.5 * E0)
+    # rank one: A = a 1^T, B = 1 b^T, D = d 1^T gives E = alpha * K (b . d) a 1^T
+    a, b, d = np.arange(1.0, 6.0), np.arange(-1.0, 2.0), np.array([2.0, -1.0, 3.0])
+    E = G2.gemm2(np.outer(a, np.ones(4)), np.outer(np.ones(4), b), np.outer(d, np.ones(6)), alpha=0.5)
+    np.testing.assert_array_equal(E, 0.5 * 4 * np.dot(b, d) * np.outer(a, np.ones(6)))
+    # beta == 0 does not read E0; row subset equals the rows of the full result
+    assert np.isfinite(G2.gemm2(A, B, D, np.full_like(E0, np.nan), 1.0, 0.0)).all()
+    full = G2.gemm2(A, B, D, E0, 1.0, 2.0, relu=True)
+    np.testing.assert_array_equal(G2.gemm2(A, B, D, E0, 1.0, 2.0, relu=True, rows=[4, 0, 2]), full[[4, 0, 2]])
+    # NaN in A B survives the ReLU
+    An = A.copy()
+    An[1, 0] = np.nan
+    assert np.isnan(G2.gemm2(An, B, D, relu=True)[1]).all()
