@@ -21,6 +21,8 @@ the path on their own workloads:
     seed 30), quantised on the GPU, e4m3 and bf16, alpha = 1, beta = 0;
   - a 3x3 convolution layer (batch 32, 56 x 56, 256 -> 256 channels, NHWC, seed 5) as an
     implicit gemm, F32 and split-bf16x3, beside a materialised im2col matrix fed to the gemm;
+  - a back-to-back pair of 256-wide layers over the same 100352 pixels, E = relu(A B) D with
+    relu(A B) kept on chip (U[-1, 1], seed 6), beside two gemm calls with the ReLU between;
   - the grouped persistent launch over 512 problems with M, N, K log-uniform in
     [16, 2048] (seed 4, matrices from seeds 4000 + p), alpha = 1, beta = 0.5,
     F32 and split-bf16x3, tile shapes tuned on the set (tgemm_batched_autotune),
@@ -193,6 +195,29 @@ def extra_rows(tg, inputs):
             "implicit_over_materialised": round((i_avg + g_avg) / avg, 3)}
         del cols, Ym, Y
     del X, Wt, Y0
+    torch.cuda.empty_cache()
+
+    # back-to-back gemm E = act(A B) D with act(A B) on chip, against two library gemms with
+    # the ReLU between (the intermediate through memory)
+    M, K, N1, N2 = nb * H * W, 256, 256, 256
+    g = torch.Generator().manual_seed(6)
+    A2, B2, D2, E2 = ((2 * torch.rand(r, c, generator=g) - 1).to(dev) for r, c in ((M, K), (K, N1), (N1, N2), (M, N2)))
+    T2 = torch.empty(M, N1, device=dev)
+    fflops = 2.0 * M * N1 * (K + N2)
+    for dt in ("f32", "x3"):
+        avg, med = _time_events(lambda: tg.gemm2(A2, B2, D2, E2, 1.0, 0.0, True, dt), 10)
+
+        def unfused():
+            tg.gemm(A2, B2, T2, 1.0, 0.0, dt)
+            torch.relu_(T2)
+            tg.gemm(T2, D2, E2, 1.0, 0.0, dt)
+        u_avg, _ = _time_events(unfused, 10)
+        out[f"gemm2_relu_{dt}_{M}x{K}x{N1}x{N2}"] = {
+            "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(fflops / (avg * 1e-3) / 1e12, 2),
+            "peak_tflops": round(PEAK_TFLOPS[dt], 1),
+            "frac_peak": round(fflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4),
+            "unfused_ms": round(u_avg, 4), "fused_over_unfused": round(u_avg / avg, 3)}
+    del A2, B2, D2, E2, T2
     torch.cuda.empty_cache()
 
     dims = inputs.grouped_dims()

@@ -166,6 +166,30 @@ int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64
 int tgemm_conv3x3(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
                   const float* X, const float* Wt, float beta, float* Y, int dtype, void* stream);
 
+/* Activations of tgemm_gemm2. */
+#define TGEMM_ACT_NONE 0
+#define TGEMM_ACT_RELU 1
+
+/*
+ * Back-to-back gemm with the intermediate kept on chip (project addition; the
+ * paper's VGG block fuses its two layers so that the intermediate stays close
+ * to the arithmetic, Section VI-A):
+ *   T = act(A B)               A: M x K (lda), B: K x N1 (ldb)
+ *   E = alpha * T D + beta * E  D: N1 x N2 (ldd), E: M x N2 (lde)
+ * act: TGEMM_ACT_NONE or TGEMM_ACT_RELU (max(x, 0), NaN kept).  All matrices
+ * row-major float, DEVICE pointers, any alignment.  T is formed in FP32, 64
+ * rows at a time, in LDS and never written to memory.  dtype: TGEMM_F32 or
+ * TGEMM_F32_BF16X3 (the x3 form of both products; T is split like any
+ * operand).  N1 <= 256, and 64*lda*4, 16*ldb*4 and 16*ldd*4 below 2^31, else
+ * TGEMM_NOT_SUPPORTED; lda < K, ldb < N1, ldd < N2 or lde < N2 give
+ * TGEMM_INVALID_VALUE.  Degenerate cases as for tgemm: M or N2 == 0 is a no-op;
+ * K, N1 or alpha == 0 gives E = beta*E without reading A, B, D; beta == 0 does
+ * not read E.
+ */
+int tgemm_gemm2(int64_t M, int64_t N1, int64_t N2, int64_t K, float alpha, const float* A, int64_t lda,
+                const float* B, int64_t ldb, int act, const float* D, int64_t ldd, float beta, float* E,
+                int64_t lde, int dtype, void* stream);
+
 /* Kernels of tgemm_conv3x3_path. */
 #define TGEMM_CONV_AUTO 0   /* as tgemm_conv3x3 */
 #define TGEMM_CONV_DIRECT 1 /* A units loaded into registers straight from X; no workspace */

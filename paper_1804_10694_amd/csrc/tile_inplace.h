@@ -201,13 +201,17 @@ struct InplaceOps<CF, MODE_F32> {
     static constexpr int NREAD = CF::TM + 4 * CF::TN;
     static constexpr int NMFMA = 4 * CF::TM * CF::TN;
 
-    __device__ __forceinline__ static void load(const char* stage, Ops& o, int g, int wm0, int wn0, int lane)
+    // A operands from an A panel `la` (packed layout), B operands from a B panel `lb`
+    __device__ __forceinline__ static void load_a(const char* la, Ops& o, int g, int wm0, int lane)
     {
         const int h = lane >> 5, l32 = lane & 31;
-        const char* lb = stage + CF::LDS_A;
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)
-            o.a[i] = *reinterpret_cast<const u32x4*>(stage + pk_slot<CF::UK>(wm0 + 32 * i + l32, 2 * g + h) * 16);
+            o.a[i] = *reinterpret_cast<const u32x4*>(la + pk_slot<CF::UK>(wm0 + 32 * i + l32, 2 * g + h) * 16);
+    }
+    __device__ __forceinline__ static void load_b(const char* lb, Ops& o, int g, int wn0, int lane)
+    {
+        const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j) {
             const int n = wn0 + 32 * j + l32;
@@ -216,6 +220,11 @@ struct InplaceOps<CF, MODE_F32> {
                 o.b[j][e] = *reinterpret_cast<const float*>(
                     lb + ip_bslot<CF>(8 * g + 4 * h + e, n / 4) * 16 + (n % 4) * 4);
         }
+    }
+    __device__ __forceinline__ static void load(const char* stage, Ops& o, int g, int wm0, int wn0, int lane)
+    {
+        load_a(stage, o, g, wm0, lane);
+        load_b(stage + CF::LDS_A, o, g, wn0, lane);
     }
 
     __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN])
@@ -254,18 +263,21 @@ struct InplaceOps<CF, MODE_X3> {
         }
     }
 
-    __device__ __forceinline__ static void load(const char* stage, Ops& o, int g, int wm0, int wn0, int lane)
+    __device__ __forceinline__ static void load_a(const char* la, Ops& o, int g, int wm0, int lane)
     {
         const int h = lane >> 5, l32 = lane & 31;
-        const char* lb = stage + CF::LDS_A;
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i) {
             const int row = wm0 + 32 * i + l32, u0 = 4 * g + 2 * h;
-            const f32x4 p = *reinterpret_cast<const f32x4*>(stage + pk_slot<CF::UK>(row, u0) * 16);
-            const f32x4 q = *reinterpret_cast<const f32x4*>(stage + pk_slot<CF::UK>(row, u0 + 1) * 16);
+            const f32x4 p = *reinterpret_cast<const f32x4*>(la + pk_slot<CF::UK>(row, u0) * 16);
+            const f32x4 q = *reinterpret_cast<const f32x4*>(la + pk_slot<CF::UK>(row, u0 + 1) * 16);
             const float x[8] = {p[0], p[1], p[2], p[3], q[0], q[1], q[2], q[3]};
             split8(x, o.ah[i], o.al[i]);
         }
+    }
+    __device__ __forceinline__ static void load_b(const char* lb, Ops& o, int g, int wn0, int lane)
+    {
+        const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j) {
             const int n = wn0 + 32 * j + l32;
@@ -275,6 +287,11 @@ struct InplaceOps<CF, MODE_X3> {
                 x[e] = *reinterpret_cast<const float*>(lb + ip_bslot<CF>(16 * g + 8 * h + e, n / 4) * 16 + (n % 4) * 4);
             split8(x, o.bh[j], o.bl[j]);
         }
+    }
+    __device__ __forceinline__ static void load(const char* stage, Ops& o, int g, int wm0, int wn0, int lane)
+    {
+        load_a(stage, o, g, wm0, lane);
+        load_b(stage + CF::LDS_A, o, g, wn0, lane);
     }
 
     __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN])

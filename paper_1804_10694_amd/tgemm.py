@@ -41,6 +41,8 @@ lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp,
 lib.tgemm_conv3x3.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p]
 lib.tgemm_conv3x3_path.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _i32, _p]
 lib.tgemm_conv3x3_packed_shape.argtypes = [_i32, _i32, _p, _p, _p, _p]
+lib.tgemm_gemm2.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _i32, _p, _i64, _f32, _p, _i64,
+                            _i32, _p]
 lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
                                          _pf32, _pp, _pi64, _i32, _i32, _i32, _p]
 lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
@@ -143,6 +145,27 @@ def gemm(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None):
     _check(lib.tgemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dt, _stream_handle(stream)),
            "tgemm")
     return C
+
+
+ACT_NONE, ACT_RELU = 0, 1
+
+
+def gemm2(A, B, D, E, alpha=1.0, beta=0.0, relu=False, dtype="f32", stream=None):
+    """E = alpha * act(A@B) @ D + beta*E in place, act = ReLU if relu (tgemm_gemm2): the
+    intermediate act(A@B) stays on chip.  Row-major float32 device matrices (unit column stride)."""
+    M, K = A.shape
+    N1 = B.shape[1]
+    N2 = D.shape[1]
+    if B.shape[0] != K or D.shape[0] != N1 or tuple(E.shape) != (M, N2):
+        raise ValueError(f"shapes do not chain: {tuple(A.shape)} {tuple(B.shape)} {tuple(D.shape)} "
+                         f"-> {tuple(E.shape)}")
+    pa, lda = _mat(A, "A", torch.float32)
+    pb, ldb = _mat(B, "B", torch.float32)
+    pd, ldd = _mat(D, "D", torch.float32)
+    pe, lde = _mat(E, "E", torch.float32)
+    _check(lib.tgemm_gemm2(M, N1, N2, K, alpha, pa, lda, pb, ldb, ACT_RELU if relu else ACT_NONE, pd, ldd,
+                           beta, pe, lde, _dtype_code(dtype), _stream_handle(stream)), "tgemm_gemm2")
+    return E
 
 
 def gemm_raw(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dtype, stream=None):
