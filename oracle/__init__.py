@@ -18,9 +18,12 @@ Contents
                   of Section VI-A as an implicit gemm's reference).
   gemm2           FP64 back-to-back gemm alpha * act(A B) D + beta * E0
                   (the fused layer pair of Section VI-A's VGG block).
+  contract        FP64 binary tensor contraction over labelled modes (the
+                  Baryon benchmark's operation, Section VI-A).
 """
 from .gemm import gemm, gemm_rows, num_threads, normwise_error, lib_path  # noqa: F401
 from . import precision  # noqa: F401
 from . import mlp  # noqa: F401
 from . import conv  # noqa: F401
 from . import gemm2  # noqa: F401
+from . import contract  # noqa: F401

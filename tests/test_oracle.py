@@ -485,3 +485,51 @@ def test_gemm2_closed_forms():
     An = A.copy()
     An[1, 0] = np.nan
     assert np.isnan(G2.gemm2(An, B, D, relu=True)[1]).all()
+
+
+# ---------------------------------------------------------------- tensor contraction oracle
+from oracle import contract as OT  # noqa: E402
+
+
+def _int_tensor(shape, seed):
+    return np.random.default_rng(seed).integers(-3, 4, shape).astype(np.float64)
+
+
+def test_contract_brute_force_tiny():
+    # C[x, a, b] = sum_c A[c, x, a] B[x, b, c] (batch x, row a, column b, contracted c), by loops
+    X, Ad, Bd, Cd = 2, 3, 4, 5
+    A = _int_tensor((Cd, X, Ad), 101)
+    B = _int_tensor((X, Bd, Cd), 102)
+    C0 = _int_tensor((X, Ad, Bd), 103)
+    ref = np.zeros((X, Ad, Bd))
+    for x in range(X):
+        for a in range(Ad):
+            for b in range(Bd):
+                s = sum(A[c, x, a] * B[x, b, c] for c in range(Cd))
+                ref[x, a, b] = 2.0 * s + 0.5 * C0[x, a, b]
+    got = OT.contract(A, [7, 1, 3], B, [1, 4, 7], [1, 3, 4], C0, 2.0, 0.5)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_contract_matrix_and_batched_cases_are_gemms():
+    A = _int_tensor((6, 5), 104)
+    B = _int_tensor((5, 4), 105)
+    C0 = _int_tensor((6, 4), 106)
+    np.testing.assert_array_equal(OT.contract(A, [0, 1], B, [1, 2], [0, 2], C0, 1.5, -1.0),
+                                  oracle.gemm(A, B, C0, 1.5, -1.0))
+    # batch of 3 matrix products, batch mode leading in all three tensors
+    Ab, Bb = _int_tensor((3, 6, 5), 107), _int_tensor((3, 5, 4), 108)
+    got = OT.contract(Ab, [9, 0, 1], Bb, [9, 1, 2], [9, 0, 2])
+    for t in range(3):
+        np.testing.assert_array_equal(got[t], oracle.gemm(Ab[t], Bb[t]))
+
+
+def test_contract_relabelled_output_is_a_transpose_and_beta_zero_skips_c0():
+    A, B = _int_tensor((4, 3, 5), 109), _int_tensor((5, 2), 110)
+    C = OT.contract(A, [0, 1, 2], B, [2, 3], [0, 1, 3])
+    Ct = OT.contract(A, [0, 1, 2], B, [2, 3], [3, 1, 0])
+    np.testing.assert_array_equal(Ct, np.transpose(C, (2, 1, 0)))
+    assert np.isfinite(OT.contract(A, [0, 1, 2], B, [2, 3], [0, 1, 3], np.full((4, 3, 2), np.nan))).all()
+    # no contracted mode: an outer product
+    u, v = _int_tensor((4,), 111), _int_tensor((3,), 112)
+    np.testing.assert_array_equal(OT.contract(u, [0], v, [1], [0, 1]), np.outer(u, v))
