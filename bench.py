@@ -23,6 +23,8 @@ the path on their own workloads:
     implicit gemm, F32 and split-bf16x3, beside a materialised im2col matrix fed to the gemm;
   - a back-to-back pair of 256-wide layers over the same 100352 pixels, E = relu(A B) D with
     relu(A B) kept on chip (U[-1, 1], seed 6), beside two gemm calls with the ReLU between;
+  - two synthetic tensor contractions (seed 7): 64 products of 256^3 whose operands need
+    reordering, and 16384 site blocks of 12 x 12 x 12;
   - the grouped persistent launch over 512 problems with M, N, K log-uniform in
     [16, 2048] (seed 4, matrices from seeds 4000 + p), alpha = 1, beta = 0.5,
     F32 and split-bf16x3, tile shapes tuned on the set (tgemm_batched_autotune),
@@ -218,6 +220,32 @@ def extra_rows(tg, inputs):
             "frac_peak": round(fflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4),
             "unfused_ms": round(u_avg, 4), "fused_over_unfused": round(u_avg / avg, 3)}
     del A2, B2, D2, E2, T2
+    torch.cuda.empty_cache()
+
+    # tensor contractions (synthetic; the Baryon benchmark's own tensors are not available):
+    # a batched contraction whose operands need reordering, and many 12 x 12 site blocks
+    g = torch.Generator().manual_seed(7)
+    work = {
+        "contract_permuted_64x256x256x256": (([1, 9, 0], (256, 64, 256)), ([9, 2, 1], (64, 256, 256)),
+                                             ([9, 0, 2], (64, 256, 256))),
+        "contract_site_blocks_16384x12x12x12": (([7, 0, 1], (16384, 12, 12)), ([7, 1, 2], (16384, 12, 12)),
+                                                ([7, 0, 2], (16384, 12, 12))),
+    }
+    for name, ((ma, ea), (mb, eb), (mc, ec)) in work.items():
+        At = (2 * torch.rand(ea, generator=g) - 1).to(dev)
+        Bt = (2 * torch.rand(eb, generator=g) - 1).to(dev)
+        Ct = torch.zeros(ec, device=dev)
+        ext = dict(zip(ma, ea))
+        ext.update(zip(mb, eb))
+        cfl = 2.0
+        for m in ext:
+            cfl *= ext[m]
+        for dt in ("f32", "x3"):
+            avg, med = _time_events(lambda: tg.contract(At, ma, Bt, mb, Ct, mc, 1.0, 0.0, dt), 10)
+            out[f"{name}_{dt}"] = {"avg_ms": round(avg, 4), "median_ms": round(med, 4),
+                                   "tflops": round(cfl / (avg * 1e-3) / 1e12, 3)}
+        del At, Bt, Ct
+    tg.shutdown()
     torch.cuda.empty_cache()
 
     dims = inputs.grouped_dims()

@@ -190,6 +190,31 @@ int tgemm_gemm2(int64_t M, int64_t N1, int64_t N2, int64_t K, float alpha, const
                 const float* B, int64_t ldb, int act, const float* D, int64_t ldd, float beta, float* E,
                 int64_t lde, int dtype, void* stream);
 
+/*
+ * Binary tensor contraction over labelled modes (project addition; the
+ * paper's Baryon benchmark is a dense tensor contraction, Section VI-A):
+ *   C[modes_c] = alpha * sum A[modes_a] * B[modes_b] + beta * C[modes_c]
+ * summed over the modes of A and B that C does not have.  Each tensor is
+ * dense and row-major (its last mode contiguous), float, a DEVICE pointer;
+ * n* modes (0 to 8) with integer labels modes_* and extents extents_* (host
+ * arrays).  A mode in A, B and C is a batch mode, in A and C a row mode, in
+ * B and C a column mode, in A and B a contracted mode.  The contraction runs
+ * as a batch of row x contracted by contracted x column gemms (tgemm for one,
+ * tgemm_batched_strided for several; dtype TGEMM_F32 or TGEMM_F32_BF16X3); an
+ * operand not already laid out [batch, row, contracted] ([batch, contracted,
+ * column] for B, [batch, row, column] for C; batch, row and column modes in
+ * C's order, contracted modes in A's) is first copied into that order in a
+ * per-(device, stream) workspace the library owns (not grown under stream
+ * capture: TGEMM_CAPTURE_UNPLANNED).  Returns TGEMM_INVALID_VALUE for a
+ * negative extent, a mode twice in one tensor or one label with two
+ * extents; TGEMM_NOT_SUPPORTED for more than 8 modes, a mode in only one
+ * tensor, or more than 2^24 batch elements.  Empty C is a no-op; no
+ * contracted element or alpha == 0 gives C = beta*C without reading A or B.
+ */
+int tgemm_contract(int na, const int* modes_a, const int64_t* extents_a, const float* A, int nb,
+                   const int* modes_b, const int64_t* extents_b, const float* B, int nc, const int* modes_c,
+                   const int64_t* extents_c, float* C, float alpha, float beta, int dtype, void* stream);
+
 /* Kernels of tgemm_conv3x3_path. */
 #define TGEMM_CONV_AUTO 0   /* as tgemm_conv3x3 */
 #define TGEMM_CONV_DIRECT 1 /* A units loaded into registers straight from X; no workspace */
@@ -237,6 +262,20 @@ int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, 
                              const void* const* B, const int64_t* ldb, const float* beta,
                              float* const* C, const int64_t* ldc, int dtype, int threshold,
                              int large, void* stream);
+
+/*
+ * tgemm_batched over `count` problems of one shape at fixed element strides
+ * (project addition): problem p is C + p*strideC = alpha * (A + p*strideA)
+ * (B + p*strideB) + beta * (C + p*strideC), float operands (F32 or x3).
+ * The plan is cached under these 17 scalars, so a repeated call costs
+ * constant host time whatever the count (tgemm_batched hashes every
+ * problem's arguments).  Problems' C blocks must not overlap (strideC >=
+ * (M-1)*ldc + N when count > 1) and strides must be >= 0, else
+ * TGEMM_INVALID_VALUE; otherwise as tgemm_batched.
+ */
+int tgemm_batched_strided(int64_t count, int64_t M, int64_t N, int64_t K, float alpha, const void* A,
+                          int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+                          float beta, float* C, int64_t ldc, int64_t strideC, int dtype, void* stream);
 
 /*
  * Plan-shape autotuner of the grouped launch (project addition; the paper

@@ -691,8 +691,78 @@ int batched_run(int64_t count, const int64_t* M, const int64_t* N, const int64_t
     return launch_plan(it->second, s);
 }
 
+// Uniform problems at fixed strides: the plan is keyed by the 17 scalars that
+// define the set, so a cached launch costs O(1) host work whatever the count.
+int strided_run(int64_t count, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+                int64_t sA, const void* B, int64_t ldb, int64_t sB, float beta, float* C, int64_t ldc, int64_t sC,
+                int dtype, hipStream_t s)
+{
+    if (dtype != TGEMM_F32 && dtype != TGEMM_F32_BF16X3) return TGEMM_NOT_SUPPORTED;
+    if (count < 0 || count > (1 << 24) || sA < 0 || sB < 0 || sC < 0) return TGEMM_INVALID_VALUE;
+    if (count == 0 || M == 0 || N == 0) return validate_gemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    int rc = validate_gemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (rc != TGEMM_SUCCESS) return rc;
+    // problems' C blocks must not overlap (they are written concurrently)
+    if (count > 1 && sC < (M - 1) * ldc + N) return TGEMM_INVALID_VALUE;
+    const std::vector<uint64_t> key = {0x5354524944454431ull, (uint64_t)count, (uint64_t)dtype,
+                                       (uint64_t)M, (uint64_t)N, (uint64_t)K, fbits(alpha), fbits(beta),
+                                       (uint64_t)(uintptr_t)A, (uint64_t)lda, (uint64_t)sA,
+                                       (uint64_t)(uintptr_t)B, (uint64_t)ldb, (uint64_t)sB,
+                                       (uint64_t)(uintptr_t)C, (uint64_t)ldc, (uint64_t)sC};
+    const uint64_t h = fnv(key);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_plans.find(h);
+    if (it == g_plans.end() || it->second.key != key || it->second.device != dev) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            return TGEMM_CAPTURE_UNPLANNED;
+        rc = ensure_device(s);
+        if (rc != TGEMM_SUCCESS) return rc;
+        if (it != g_plans.end()) {
+            free_plan(it->second);
+            g_plans.erase(it);
+        }
+        const size_t n = (size_t)count;
+        std::vector<int64_t> vM(n, M), vN(n, N), vK(n, K), vlda(n, lda), vldb(n, ldb), vldc(n, ldc);
+        std::vector<float> va(n, alpha), vb(n, beta);
+        std::vector<const void*> pa(n), pb(n);
+        std::vector<float*> pc(n);
+        const int64_t es = 4;  // float32 operands
+        for (size_t p = 0; p < n; ++p) {
+            pa[p] = static_cast<const char*>(A) + (int64_t)p * sA * es;
+            pb[p] = static_cast<const char*>(B) + (int64_t)p * sB * es;
+            pc[p] = C + (int64_t)p * sC;
+        }
+        const uint64_t dk = dims_key(count, vM.data(), vN.data(), vK.data(), va.data(), pa.data(), vlda.data(),
+                                     pb.data(), vldb.data(), dtype);
+        auto tuned = g_tuned_shape.find(dk);
+        const Shape shape = tuned != g_tuned_shape.end() ? tuned->second : kDefaultShape;
+        Plan plan;
+        plan.key = key;
+        plan.dims = dk;
+        rc = build_plan(count, vM.data(), vN.data(), vK.data(), va.data(), pa.data(), vlda.data(), pb.data(),
+                        vldb.data(), vb.data(), pc.data(), vldc.data(), dtype, shape, &plan);
+        if (rc != TGEMM_SUCCESS) {
+            free_plan(plan);
+            return rc;
+        }
+        it = g_plans.emplace(h, std::move(plan)).first;
+    }
+    return launch_plan(it->second, s);
+}
+
 }  // namespace
 }  // namespace tg
+
+extern "C" int tgemm_batched_strided(int64_t count, int64_t M, int64_t N, int64_t K, float alpha, const void* A,
+                                     int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+                                     float beta, float* C, int64_t ldc, int64_t strideC, int dtype, void* stream)
+{
+    return tg::strided_run(count, M, N, K, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc, strideC, dtype,
+                           static_cast<hipStream_t>(stream));
+}
 
 extern "C" int tgemm_batched(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                              const float* alpha, const void* const* A, const int64_t* lda,
@@ -844,4 +914,5 @@ extern "C" void tgemm_shutdown(void)
     g_plans.clear();
     g_tuned_shape.clear();
     packed_shutdown();
+    contract_shutdown();
 }

@@ -37,6 +37,7 @@ size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype);
 // reach of a buffer resource's 32-bit offsets.
 bool packed_k_ok(int64_t K, int dtype);
 void packed_shutdown();
+void contract_shutdown();  // frees the contraction workspaces (contract.hip)
 void packed_release(hipStream_t s);  // frees the workspace of one stream
 // Per (device, stream) packing workspace of at least `bytes`, grown on demand
 // (never under stream capture: TGEMM_CAPTURE_UNPLANNED).

@@ -41,6 +41,9 @@ lib.tgemm_batched.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp,
 lib.tgemm_conv3x3.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p]
 lib.tgemm_conv3x3_path.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _i32, _p]
 lib.tgemm_conv3x3_packed_shape.argtypes = [_i32, _i32, _p, _p, _p, _p]
+lib.tgemm_batched_strided.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _i64, _p, _i64, _i64, _f32, _p, _i64,
+                                      _i64, _i32, _p]
+lib.tgemm_contract.argtypes = [_i32, _p, _p, _p, _i32, _p, _p, _p, _i32, _p, _p, _p, _f32, _f32, _i32, _p]
 lib.tgemm_gemm2.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _i32, _p, _i64, _f32, _p, _i64,
                             _i32, _p]
 lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
@@ -166,6 +169,42 @@ def gemm2(A, B, D, E, alpha=1.0, beta=0.0, relu=False, dtype="f32", stream=None)
     _check(lib.tgemm_gemm2(M, N1, N2, K, alpha, pa, lda, pb, ldb, ACT_RELU if relu else ACT_NONE, pd, ldd,
                            beta, pe, lde, _dtype_code(dtype), _stream_handle(stream)), "tgemm_gemm2")
     return E
+
+
+def gemm_batched_strided(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+    """C[p] = alpha*A[p]@B[p] + beta*C[p] for 3-D float32 device tensors (batch, rows, cols) with
+    unit column stride (tgemm_batched_strided)."""
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if not t.is_cuda or t.dtype != torch.float32 or t.dim() != 3 or (t.shape[2] > 1 and t.stride(2) != 1):
+            raise ValueError(f"{name} must be a 3-D float32 device tensor with unit column stride")
+    P, M, K = A.shape
+    N = B.shape[2]
+    if tuple(B.shape) != (P, K, N) or tuple(C.shape) != (P, M, N):
+        raise ValueError("shapes must be A (P, M, K), B (P, K, N), C (P, M, N)")
+    ld = lambda t: t.stride(1) if t.shape[1] > 1 else max(t.shape[2], 1)   # noqa: E731
+    _check(lib.tgemm_batched_strided(P, M, N, K, alpha, A.data_ptr(), ld(A), A.stride(0), B.data_ptr(), ld(B),
+                                     B.stride(0), beta, C.data_ptr(), ld(C), C.stride(0), _dtype_code(dtype),
+                                     _stream_handle(stream)), "tgemm_batched_strided")
+    return C
+
+
+def contract(A, modes_a, B, modes_b, C, modes_c, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+    """C[modes_c] = alpha * sum A[modes_a] * B[modes_b] + beta * C (tgemm_contract): contiguous
+    float32 device tensors, modes given as sequences of integer labels."""
+    def arrs(t, modes, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 device tensor")
+        if len(modes) != t.dim():
+            raise ValueError(f"{name} has {t.dim()} modes, {len(modes)} labels given")
+        m = (ctypes.c_int32 * max(len(modes), 1))(*modes)
+        e = (ctypes.c_int64 * max(t.dim(), 1))(*t.shape)
+        return len(modes), m, e, t.data_ptr()
+    na, ma, ea, pa = arrs(A, modes_a, "A")
+    nb, mb, eb, pb = arrs(B, modes_b, "B")
+    nc, mc, ec, pc = arrs(C, modes_c, "C")
+    _check(lib.tgemm_contract(na, ma, ea, pa, nb, mb, eb, pb, nc, mc, ec, pc, alpha, beta, _dtype_code(dtype),
+                              _stream_handle(stream)), "tgemm_contract")
+    return C
 
 
 def gemm_raw(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dtype, stream=None):

@@ -264,3 +264,35 @@ def test_autotune_and_forced_shape_reject_bad_arguments(tg):
         tg.gemm_batched_autotune([A], [A], [A.clone()], [1.0], [0.0], "f32", reps=0)
     with pytest.raises(tg.TgemmError):
         tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "large": 0})
+
+
+@pytest.mark.parametrize("dims", [(300, 12, 12, 12), (7, 130, 70, 33), (40, 64, 64, 64)])
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_strided_batched_bit_exact(tg, dtype, dims):
+    # tgemm_batched_strided: P problems of one shape at fixed strides (here slices of 3-D tensors,
+    # C with a row stride wider than N), bit-exact on integers, twice in a row (cached plan)
+    P, M, N, K = dims
+    g = torch.Generator().manual_seed(sum(dims))
+    A = torch.randint(-8, 9, (P, M, K), generator=g).float()
+    B = torch.randint(-8, 9, (P, K, N), generator=g).float()
+    C0 = torch.randint(-8, 9, (P, M, N), generator=g).float()
+    Cbuf = torch.full((P, M, N + 3), float("nan"), device=DEV)
+    Cd = Cbuf[:, :, :N]
+    Ad, Bd = A.to(DEV), B.to(DEV)
+    for rep in range(2):
+        Cd.copy_(C0.to(DEV))
+        tg.gemm_batched_strided(Ad, Bd, Cd, 1.5, 0.5, dtype)
+        torch.cuda.synchronize()
+        got = Cd.cpu().numpy().astype(np.float64)
+        for p in range(P):
+            np.testing.assert_array_equal(got[p], oracle.gemm(A[p], B[p], C0[p], 1.5, 0.5),
+                                          err_msg=f"rep {rep} problem {p}")
+    assert torch.isnan(Cbuf[:, :, N:]).all()
+
+
+def test_strided_batched_rejects_overlapping_outputs(tg):
+    A = torch.zeros(4, 8, 8, device=DEV)
+    C = torch.zeros(64, device=DEV)
+    rc = tg.lib.tgemm_batched_strided(4, 8, 8, 8, 1.0, A.data_ptr(), 8, 64, A.data_ptr(), 8, 64, 0.0,
+                                      C.data_ptr(), 8, 8, 0, None)
+    assert rc == tg.INVALID_VALUE
