@@ -269,7 +269,8 @@ int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, 
  * (B + p*strideB) + beta * (C + p*strideC), float operands (F32 or x3).
  * The plan is cached under these 17 scalars, so a repeated call costs
  * constant host time whatever the count (tgemm_batched hashes every
- * problem's arguments).  Problems' C blocks must not overlap (strideC >=
+ * problem's arguments).  Problems with M and N at most 32 skip the plan: one
+ * wave per problem multiplies from registers with FP32 MFMAs (both dtypes).  Problems' C blocks must not overlap (strideC >=
  * (M-1)*ldc + N when count > 1) and strides must be >= 0, else
  * TGEMM_INVALID_VALUE; otherwise as tgemm_batched.
  */

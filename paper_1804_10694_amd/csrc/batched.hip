@@ -205,6 +205,59 @@ __global__ void __launch_bounds__(GroupPacked<MODE>::NT, 1)
     }
 }
 
+// Uniform small problems at fixed strides (M and N at most T = 16 or 32):
+// one problem per wave, no LDS.  Each step of K is one MFMA whose operands are
+// loaded straight into the lanes that own them (T = 16: v_mfma_f32_16x16x4f32,
+// lane l holds A[l % 16][k + l / 16] and B[k + l / 16][l % 16]; T = 32:
+// v_mfma_f32_32x32x2f32, A[l % 32][k + l / 32] and B[k + l / 32][l % 32]);
+// out-of-range elements load as zero and out-of-range outputs are not stored.
+// Both forms compute in FP32 here: these products are bound by memory, not by
+// the matrix cores.
+struct SmallArgs {
+    const float* A;
+    const float* B;
+    float* C;
+    int64_t lda, ldb, ldc, sA, sB, sC, count;
+    int M, N, K;
+    float alpha, beta;
+};
+
+template <int T>
+__global__ void __launch_bounds__(256) small_batched_kernel(SmallArgs a)
+{
+    constexpr int KS = 64 / T;  // k per MFMA
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // one problem per wave
+    if (p >= a.count) return;                                        // the whole wave leaves
+    const float* A = a.A + p * a.sA;
+    const float* B = a.B + p * a.sB;
+    float* C = a.C + p * a.sC;
+    const int i = lane % T, kk = lane / T;
+    typedef float accv __attribute__((ext_vector_type(T == 16 ? 4 : 16)));
+    accv acc;
+#pragma unroll
+    for (int r = 0; r < (T == 16 ? 4 : 16); ++r) acc[r] = 0.f;
+    const int K = a.alpha != 0.f ? a.K : 0;  // alpha == 0: A and B are not read
+    for (int k0 = 0; k0 < K; k0 += KS) {
+        const int k = k0 + kk;
+        const float av = (i < a.M && k < a.K) ? A[(int64_t)i * a.lda + k] : 0.f;
+        const float bv = (i < a.N && k < a.K) ? B[(int64_t)k * a.ldb + i] : 0.f;
+        if constexpr (T == 16) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    const bool read_c = a.beta != 0.f;
+#pragma unroll
+    for (int r = 0; r < (T == 16 ? 4 : 16); ++r) {
+        const int row = (T == 16) ? 4 * (lane / 16) + r : 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+        const int col = lane % T;
+        if (row >= a.M || col >= a.N) continue;
+        float* c = C + (int64_t)row * a.ldc + col;
+        float v = a.alpha * acc[r];
+        if (read_c) v = fmaf(a.beta, *c, v);
+        *c = v;
+    }
+}
+
 // Persistent kernel of the in-place class.
 template <int MODE>
 __global__ void __launch_bounds__(GroupInplace<MODE>::NT, kInplaceOcc<MODE>)
@@ -704,6 +757,17 @@ int strided_run(int64_t count, int64_t M, int64_t N, int64_t K, float alpha, con
     if (rc != TGEMM_SUCCESS) return rc;
     // problems' C blocks must not overlap (they are written concurrently)
     if (count > 1 && sC < (M - 1) * ldc + N) return TGEMM_INVALID_VALUE;
+    if (M <= 32 && N <= 32) {
+        // small products: one wave each, no plan
+        if ((rc = ensure_device(s)) != TGEMM_SUCCESS) return rc;
+        if (K > INT32_MAX) return TGEMM_NOT_SUPPORTED;
+        SmallArgs sa{static_cast<const float*>(A), static_cast<const float*>(B), C, lda, ldb, ldc, sA, sB, sC,
+                     count, (int)M, (int)N, (int)K, alpha, beta};
+        const unsigned blocks = (unsigned)((count + 3) / 4);
+        if (M <= 16 && N <= 16) hipLaunchKernelGGL(small_batched_kernel<16>, dim3(blocks), dim3(256), 0, s, sa);
+        else hipLaunchKernelGGL(small_batched_kernel<32>, dim3(blocks), dim3(256), 0, s, sa);
+        return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
+    }
     const std::vector<uint64_t> key = {0x5354524944454431ull, (uint64_t)count, (uint64_t)dtype,
                                        (uint64_t)M, (uint64_t)N, (uint64_t)K, fbits(alpha), fbits(beta),
                                        (uint64_t)(uintptr_t)A, (uint64_t)lda, (uint64_t)sA,

@@ -266,7 +266,9 @@ def test_autotune_and_forced_shape_reject_bad_arguments(tg):
         tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "large": 0})
 
 
-@pytest.mark.parametrize("dims", [(300, 12, 12, 12), (7, 130, 70, 33), (40, 64, 64, 64)])
+# small products (M, N <= 16 and <= 32: one wave each) and planned ones
+@pytest.mark.parametrize("dims", [(300, 12, 12, 12), (33, 16, 5, 9), (50, 1, 16, 300), (65, 32, 17, 40),
+                                  (9, 24, 32, 3), (7, 130, 70, 33), (40, 64, 64, 64), (5, 33, 8, 20)])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_strided_batched_bit_exact(tg, dtype, dims):
     # tgemm_batched_strided: P problems of one shape at fixed strides (here slices of 3-D tensors,
@@ -296,3 +298,13 @@ def test_strided_batched_rejects_overlapping_outputs(tg):
     rc = tg.lib.tgemm_batched_strided(4, 8, 8, 8, 1.0, A.data_ptr(), 8, 64, A.data_ptr(), 8, 64, 0.0,
                                       C.data_ptr(), 8, 8, 0, None)
     assert rc == tg.INVALID_VALUE
+
+
+def test_strided_small_alpha_zero_reads_nothing(tg):
+    # small-product path: alpha == 0 gives beta * C with A and B (NaN here) unread
+    A = torch.full((10, 12, 12), float("nan"), device=DEV)
+    C0 = torch.randint(-8, 9, (10, 12, 12)).float()
+    C = C0.to(DEV)
+    tg.gemm_batched_strided(A, A, C, 0.0, 0.5)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy(), (0.5 * C0).numpy())
