@@ -123,6 +123,26 @@ def cpu_baseline(A, B, C0, dev_results, seconds):
     return base, errors
 
 
+def measured_peaks(tg):
+    """What the chip delivers at its running clock: the matrix-core probe (independent MFMA
+    chains on every SIMD) per dtype, and a 1 GiB device copy for HBM (read + write bytes)."""
+    import torch
+    dev = torch.device("cuda:0")
+    sink = torch.zeros(8192, device=dev)
+    out = {}
+    for dt, key in (("f32", "f32_mfma_tflops"), ("bf16", "bf16_mfma_tflops"), ("fp8", "fp8_mfma_tflops")):
+        fl = tg.mfma_loop(dt, 10000, sink)
+        _, med = _time_events(lambda: tg.mfma_loop(dt, 10000, sink), 3, warmup=1)
+        out[key] = round(fl / (med * 1e-3) / 1e12, 1)
+    src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    _, med = _time_events(lambda: dst.copy_(src), 5, warmup=1)
+    out["hbm_copy_gbs"] = round(2 * 2 ** 30 / (med * 1e-3) / 1e9, 1)
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    return out
+
+
 def _time_events(fn, reps, warmup=2):
     import torch
     for _ in range(warmup):
@@ -383,6 +403,10 @@ def main():
 
     del devm, C
     torch.cuda.empty_cache()
+    peaks = measured_peaks(tg)
+    mp = peaks["f32_mfma_tflops"] if dt_dom == "f32" else peaks["bf16_mfma_tflops"] / 3.0
+    roofline["measured_peak"] = round(mp, 1)
+    roofline["frac_of_measured_peak"] = round(dom["tflops"] / mp, 4)
     extras = None if args.no_extras else extra_rows(tg, inputs)
 
     x3 = per_path["x3_8192x8192x8192"]
@@ -400,6 +424,7 @@ def main():
         "paths": per_path,
         "x3_over_f32": round(x3["tflops"] / f32["tflops"], 3),
         "roofline": roofline,
+        "measured_peaks": peaks,
         "cpu_baseline": base,
         "sampled_normwise_error_8192": errors,
         "extra_rows": extras,

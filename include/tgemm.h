@@ -215,6 +215,18 @@ int tgemm_contract(int na, const int* modes_a, const int64_t* extents_a, const f
                    const int* modes_b, const int64_t* extents_b, const float* B, int nc, const int* modes_c,
                    const int64_t* extents_c, float* C, float alpha, float beta, int dtype, void* stream);
 
+/*
+ * Matrix-core throughput probe (project addition; for stating achieved
+ * throughput against a measured peak as well as the datasheet one): launches
+ * 2048 workgroups of 4 waves, each wave running `iters` rounds of four
+ * independent MFMAs (F32 32x32x2, BF16 32x32x16 or FP8_E4M3 32x32x64) and
+ * writing one float per wave to `sink` (DEVICE, at least 8192 floats).
+ * *flops (host, may be NULL) receives the algorithmic flops of the launch;
+ * the caller times it.  TGEMM_NOT_SUPPORTED for other dtypes,
+ * TGEMM_INVALID_VALUE for iters < 0 or a short sink.
+ */
+int tgemm_mfma_loop(int dtype, int64_t iters, float* sink, int64_t sink_len, double* flops, void* stream);
+
 /* Kernels of tgemm_conv3x3_path. */
 #define TGEMM_CONV_AUTO 0   /* as tgemm_conv3x3 */
 #define TGEMM_CONV_DIRECT 1 /* A units loaded into registers straight from X; no workspace */

@@ -43,6 +43,7 @@ lib.tgemm_conv3x3_path.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _
 lib.tgemm_conv3x3_packed_shape.argtypes = [_i32, _i32, _p, _p, _p, _p]
 lib.tgemm_batched_strided.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _i64, _p, _i64, _i64, _f32, _p, _i64,
                                       _i64, _i32, _p]
+lib.tgemm_mfma_loop.argtypes = [_i32, _i64, _p, _i64, _p, _p]
 lib.tgemm_contract.argtypes = [_i32, _p, _p, _p, _i32, _p, _p, _p, _i32, _p, _p, _p, _f32, _f32, _i32, _p]
 lib.tgemm_gemm2.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _i32, _p, _i64, _f32, _p, _i64,
                             _i32, _p]
@@ -186,6 +187,15 @@ def gemm_batched_strided(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None)
                                      B.stride(0), beta, C.data_ptr(), ld(C), C.stride(0), _dtype_code(dtype),
                                      _stream_handle(stream)), "tgemm_batched_strided")
     return C
+
+
+def mfma_loop(dtype, iters, sink, stream=None):
+    """Launch the matrix-core throughput probe (tgemm_mfma_loop); returns its algorithmic flops.
+    `sink` is a float32 device tensor of at least 8192 elements."""
+    fl = ctypes.c_double()
+    _check(lib.tgemm_mfma_loop(_dtype_code(dtype), iters, sink.data_ptr(), sink.numel(), ctypes.byref(fl),
+                               _stream_handle(stream)), "tgemm_mfma_loop")
+    return fl.value
 
 
 def contract(A, modes_a, B, modes_b, C, modes_c, alpha=1.0, beta=0.0, dtype="f32", stream=None):
