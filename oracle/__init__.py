@@ -14,7 +14,7 @@ Contents
   normwise_error  ||X - R||_F / ||R||_F in FP64.
   mlp             FP64 ReLU MLP, MSE loss, chain-rule gradients and Adam
                   (the cost model's network).
-  conv            FP64 3x3 'same' convolution layer, NHWC (the Conv layer
+  conv            FP64 R x R 'same' convolution layer, NHWC (the Conv layer
                   of Section VI-A as an implicit gemm's reference).
   gemm2           FP64 back-to-back gemm alpha * act(A B) D + beta * E0
                   (the fused layer pair of Section VI-A's VGG block).

@@ -533,3 +533,67 @@ def test_contract_relabelled_output_is_a_transpose_and_beta_zero_skips_c0():
     # no contracted mode: an outer product
     u, v = _int_tensor((4,), 111), _int_tensor((3,), 112)
     np.testing.assert_array_equal(OT.contract(u, [0], v, [1], [0, 1]), np.outer(u, v))
+
+
+# ---------------------------------------------------------------- R x R convolution (R = 5, 7)
+@pytest.mark.parametrize("R", [5, 7])
+def test_conv2d_brute_force_tiny(R):
+    g = np.random.default_rng(120 + R)
+    X = g.integers(-3, 4, (2, 4, 5, 2)).astype(np.float64)
+    Wt = g.integers(-3, 4, (R, R, 2, 3)).astype(np.float64)
+    Y0 = g.integers(-3, 4, (2, 4, 5, 3)).astype(np.float64)
+    P = R // 2
+    nb, H, W, cin = X.shape
+    ref = np.zeros((nb, H, W, 3))
+    for n in range(nb):
+        for y in range(H):
+            for x in range(W):
+                for co in range(3):
+                    s = 0.0
+                    for dy in range(R):
+                        for dx in range(R):
+                            iy, ix = y + dy - P, x + dx - P
+                            if 0 <= iy < H and 0 <= ix < W:
+                                for ci in range(cin):
+                                    s += X[n, iy, ix, ci] * Wt[dy, dx, ci, co]
+                    ref[n, y, x, co] = -1.0 * s + 0.5 * Y0[n, y, x, co]
+    np.testing.assert_array_equal(OC.conv2d(X, Wt, Y0, -1.0, 0.5), ref)
+
+
+@pytest.mark.parametrize("R", [5, 7, 11])
+def test_conv2d_center_tap_and_delta(R):
+    g = np.random.default_rng(130 + R)
+    X = g.integers(-3, 4, (1, 6, 7, 3)).astype(np.float64)
+    Wt = np.zeros((R, R, 3, 3))
+    Wt[R // 2, R // 2] = np.eye(3)
+    np.testing.assert_array_equal(OC.conv2d(X, Wt), X)
+    # a single 1 at (y0, x0, c): output pixel (y0 + P - dy, x0 + P - dx) receives Wt[dy, dx, c, :]
+    Wr = g.integers(-3, 4, (R, R, 3, 4)).astype(np.float64)
+    D = np.zeros((1, 13, 12, 3))
+    y0, x0, P = 6, 5, R // 2
+    D[0, y0, x0, 2] = 1.0
+    Y = OC.conv2d(D, Wr)
+    expect = np.zeros_like(Y)
+    for dy in range(R):
+        for dx in range(R):
+            yy, xx = y0 + P - dy, x0 + P - dx
+            if 0 <= yy < 13 and 0 <= xx < 12:
+                expect[0, yy, xx] = Wr[dy, dx, 2]
+    np.testing.assert_array_equal(Y, expect)
+
+
+def test_conv2d_equals_gemm_on_explicit_im2col_r5():
+    g = np.random.default_rng(140)
+    X = g.integers(-3, 4, (2, 5, 6, 3)).astype(np.float64)
+    Wt = g.integers(-3, 4, (5, 5, 3, 4)).astype(np.float64)
+    nb, H, W, cin = X.shape
+    cols = np.zeros((nb * H * W, 25 * cin))
+    for n in range(nb):
+        for y in range(H):
+            for x in range(W):
+                for t in range(25):
+                    iy, ix = y + t // 5 - 2, x + t % 5 - 2
+                    if 0 <= iy < H and 0 <= ix < W:
+                        cols[(n * H + y) * W + x, t * cin:(t + 1) * cin] = X[n, iy, ix]
+    ref = oracle.gemm(cols, Wt.reshape(25 * cin, -1))
+    np.testing.assert_array_equal(OC.conv2d(X, Wt).reshape(nb * H * W, -1), ref)
