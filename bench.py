@@ -23,6 +23,8 @@ the path on their own workloads:
     implicit gemm, F32 and split-bf16x3, beside a materialised im2col matrix fed to the gemm;
   - a back-to-back pair of 256-wide layers over the same 100352 pixels, E = relu(A B) D with
     relu(A B) kept on chip (U[-1, 1], seed 6), beside two gemm calls with the ReLU between;
+  - 5 x 5 and 7 x 7 layers (batch 32, 56 x 56, 128 -> 128 channels, seed 8), and the 3 x 3
+    layer through the kernels that take the filter size at run time;
   - two synthetic tensor contractions (seed 7): 64 products of 256^3 whose operands need
     reordering, and 16384 site blocks of 12 x 12 x 12;
   - the grouped persistent launch over 512 problems with M, N, K log-uniform in
@@ -198,6 +200,7 @@ def extra_rows(tg, inputs):
         Y = Y0.clone()
         avg, med = _time_events(lambda: tg.conv3x3(X, Wt, Y, 1.0, 0.0, dt), 10)
         d_avg, _ = _time_events(lambda: tg.conv3x3(X, Wt, Y, 1.0, 0.0, dt, path="direct"), 10)
+        r_avg, _ = _time_events(lambda: tg.conv2d(X, Wt, Y, 1.0, 0.0, dt, runtime_r=True), 10)
 
         def im2col():
             Xp = torch.nn.functional.pad(X, (0, 0, 1, 1, 1, 1))
@@ -213,10 +216,25 @@ def extra_rows(tg, inputs):
             "peak_tflops": round(PEAK_TFLOPS[dt], 1),
             "frac_peak": round(cflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4),
             "direct_kernel_ms": round(d_avg, 4),
+            "runtime_filter_size_ms": round(r_avg, 4), "specialised_over_runtime": round(r_avg / avg, 3),
             "im2col_materialised_ms": round(i_avg, 4), "gemm_on_im2col_ms": round(g_avg, 4),
             "implicit_over_materialised": round((i_avg + g_avg) / avg, 3)}
         del cols, Ym, Y
     del X, Wt, Y0
+    torch.cuda.empty_cache()
+
+    # 5 x 5 and 7 x 7 layers (batch 32, 56 x 56, 128 -> 128 channels, seed 8): R at run time
+    for R in (5, 7):
+        X, Wt, Y0 = (t.to(dev) for t in inputs.conv_layer_inputs(nb, H, W, 128, 128, 8, R))
+        rflops = 2.0 * nb * H * W * 128 * R * R * 128
+        for dt in ("f32", "x3"):
+            Y = Y0.clone()
+            avg, med = _time_events(lambda: tg.conv2d(X, Wt, Y, 1.0, 0.0, dt), 10)
+            out[f"conv{R}x{R}_{dt}_b32_56x56_128"] = {
+                "avg_ms": round(avg, 4), "median_ms": round(med, 4),
+                "tflops": round(rflops / (avg * 1e-3) / 1e12, 2), "peak_tflops": round(PEAK_TFLOPS[dt], 1),
+                "frac_peak": round(rflops / (avg * 1e-3) / 1e12 / PEAK_TFLOPS[dt], 4)}
+        del X, Wt, Y0, Y
     torch.cuda.empty_cache()
 
     # back-to-back gemm E = act(A B) D with act(A B) on chip, against two library gemms with

@@ -231,6 +231,7 @@ int tgemm_mfma_loop(int dtype, int64_t iters, float* sink, int64_t sink_len, dou
 #define TGEMM_CONV_AUTO 0   /* as tgemm_conv3x3 */
 #define TGEMM_CONV_DIRECT 1 /* A units loaded into registers straight from X; no workspace */
 #define TGEMM_CONV_PACKED 2 /* + i: packed tile shape i of the dtype (tgemm_conv3x3_packed_shape) */
+#define TGEMM_CONV_RUNTIME_R 0x100 /* or-ed in: the kernel that takes the filter size at run time, also for 3 x 3 */
 
 /*
  * tgemm_conv3x3 with the kernel chosen by the caller (project addition).
@@ -249,6 +250,18 @@ int tgemm_mfma_loop(int dtype, int64_t iters, float* sink, int64_t sink_len, dou
 int tgemm_conv3x3_path(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
                        const float* X, const float* Wt, float beta, float* Y, int dtype, int path,
                        void* stream);
+
+/*
+ * R x R convolution layer (R odd, at most 31; the paper's Conv benchmark names
+ * 3, 5, 7, 9 and 11): as tgemm_conv3x3_path with Wt R x R x Cin x Cout and
+ * zero padding R / 2, so that Y keeps X's height and width; K = R*R*Cin.
+ * Kernels are specialised for R = 3 at compile time; other sizes (and 3 x 3
+ * with TGEMM_CONV_RUNTIME_R or-ed into `path`) take R at run time.
+ * TGEMM_INVALID_VALUE for an even R or R outside [1, 31]; otherwise as
+ * tgemm_conv3x3_path.
+ */
+int tgemm_conv2d(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, int64_t R, float alpha,
+                 const float* X, const float* Wt, float beta, float* Y, int dtype, int path, void* stream);
 
 /*
  * Macro-tile (bm x bn), K panel (bk) and LDS pipeline depth (stages) of packed

@@ -1,6 +1,9 @@
-// 3x3 convolution layer as an implicit gemm (the paper's Conv benchmark layer,
+// Convolution layer as an implicit gemm (the paper's Conv benchmark layer,
 // Section VI-A, and the observation there that sgemm is the building block of
-// convolutions).
+// convolutions), for R x R filters (R odd).  The 3 x 3 case is written below;
+// for R x R read R*R taps and padding R / 2.  Every kernel exists twice: with
+// R = 3 fixed at compile time (the paper credits its Conv result to such
+// filter-size specialisation) and with R taken at run time.
 //
 // Y[n, y, x, co] = alpha * sum_{dy, dx, ci} Xpad[n, y + dy, x + dx, ci] * Wt[dy, dx, ci, co]
 //                  + beta * Y[n, y, x, co]
@@ -36,12 +39,24 @@ namespace tg {
 
 int ensure_device(hipStream_t stream);
 
-// NHWC input geometry; taps are 3 x 3 with padding 1, stride 1.
+// NHWC input geometry and the filter size R (odd; padding R / 2, stride 1).
 struct ConvGeom {
-    int H, W, C;
+    int H, W, C, R;
 };
 
-template <class CF>
+// Tap t of an R x R filter (row-major over dy, dx) as an offset from the output
+// pixel.  FR > 0 fixes R at compile time (divisions by a constant); FR == 0
+// takes R from the geometry.
+template <int FR>
+__device__ __forceinline__ void tap_offset(int tap, const ConvGeom& g, int& dy, int& dx)
+{
+    const int R = FR > 0 ? FR : g.R;
+    const int q = tap / R;
+    dy = q - R / 2;
+    dx = tap - q * R - R / 2;
+}
+
+template <class CF, int FR>
 struct ConvPanel : Panel<CF> {
     using Geom = ConvGeom;
     static constexpr int KU = CF::KU, UK = CF::UK, NT = CF::NT;
@@ -75,7 +90,8 @@ struct ConvPanel : Panel<CF> {
             for (int e = 0; e < KU; ++e) v[e] = 0.f;
             if (pix[p] >= 0 && kb < a.K) {
                 const int tap = kb / g.C, ci = kb - tap * g.C;
-                const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
+                int dy, dx;
+                tap_offset<FR>(tap, g, dy, dx);
                 const int iy = py[p] + dy, ix = px[p] + dx;
                 if (iy >= 0 && iy < g.H && ix >= 0 && ix < g.W) {
                     const float* src = X + (int64_t)(pix[p] + dy * g.W + dx) * g.C + ci;
@@ -93,14 +109,14 @@ struct ConvPanel : Panel<CF> {
     }
 };
 
-template <class CF>
-__global__ void __launch_bounds__(CF::NT) conv3x3_kernel(GemmArgs a, ConvGeom g)
+template <class CF, int FR>
+__global__ void __launch_bounds__(CF::NT) conv_kernel(GemmArgs a, ConvGeom g)
 {
     __shared__ __attribute__((aligned(16))) char lds[CF::LDS_BYTES];
     const TileCoord tc = map_tile(blockIdx.x, a.tiles_m, a.tiles_n, a.group_m, a.xcd_remap);
     const int m0 = tc.tm * CF::BM, n0 = tc.tn * CF::BN;
-    if (m0 + CF::BM <= a.M && n0 + CF::BN <= a.N) tile_body<CF, false, ConvPanel<CF>>(a, m0, n0, lds, g);
-    else tile_body<CF, true, ConvPanel<CF>>(a, m0, n0, lds, g);
+    if (m0 + CF::BM <= a.M && n0 + CF::BN <= a.N) tile_body<CF, false, ConvPanel<CF, FR>>(a, m0, n0, lds, g);
+    else tile_body<CF, true, ConvPanel<CF, FR>>(a, m0, n0, lds, g);
 }
 
 // A panels of the packed kernel, read from the NHWC input (X, or its bf16 hi
@@ -109,7 +125,7 @@ __global__ void __launch_bounds__(CF::NT) conv3x3_kernel(GemmArgs a, ConvGeom g)
 // ig * (64 / UK) + lane / UK of the tile (ig = wave * A_INSTR + i) and the
 // unit u of that row given by the swizzle of tile_packed.h (pk_slot), i.e.
 // channels [ci, ci + KU) of tap `tap` for k = panel * BK + u * KU.
-template <class CF>
+template <class CF, int FR>
 struct ConvRowsA {
     using Geom = ConvGeom;
     static constexpr int NI = CF::A_INSTR, UK = CF::UK, KU = CF::KU;
@@ -118,12 +134,14 @@ struct ConvRowsA {
 
     __amdgpu_buffer_rsrc_t r, rl;
     int wave, K, H, W, C;
+    ConvGeom g;
     int ku[NI];                   // first k of this lane's unit within a panel
     int pix[NI], py[NI], px[NI];  // output pixel of this lane's row (-1 past M), its y and x
 
-    __device__ __forceinline__ void init(const PackedArgs& a, int m0, int lane, int wave_, const Geom& g)
+    __device__ __forceinline__ void init(const PackedArgs& a, int m0, int lane, int wave_, const Geom& geom)
     {
         wave = wave_;
+        g = geom;
         K = a.K;
         H = g.H;
         W = g.W;
@@ -150,7 +168,8 @@ struct ConvRowsA {
             const int ig = wave * NI + i;
             const int k = panel * CF::BK + ku[i];
             const int tap = k / C, ci = k - tap * C;
-            const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
+            int dy, dx;
+            tap_offset<FR>(tap, g, dy, dx);
             const int iy = py[i] + dy, ix = px[i] + dx;
             const bool in = pix[i] >= 0 && k < K && iy >= 0 && iy < H && ix >= 0 && ix < W;
             const int voff = in ? ((pix[i] + dy * W + dx) * C + ci) * CF::ES : OOB;
@@ -164,25 +183,28 @@ struct ConvRowsA {
     }
 };
 
-template <class CF>
-__global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) conv3x3_packed_kernel(PackedArgs a, ConvGeom g)
+template <class CF, int FR>
+__global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) conv_packed_kernel(PackedArgs a, ConvGeom g)
 {
     static_assert(kPackK % CF::BK == 0 && kPackRows % CF::BN == 0, "panels and tiles divide the packing padding");
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
     const TileCoord tc = map_tile(blockIdx.x, a.tiles_m, a.tiles_n, a.group_m, a.xcd_remap);
-    packed_tile<CF, ConvRowsA<CF>>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds, g);
+    packed_tile<CF, ConvRowsA<CF, FR>>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds, g);
 }
 
 namespace {
 
+// Every kernel exists twice: specialised for 3 x 3 filters (FR = 3) and for a
+// filter size given at run time (FR = 0).
 struct ConvPacked {
     int dtype, mode, BM, BN, BK, NS, threads;
-    void (*kernel)(PackedArgs, ConvGeom);
+    void (*kernel[2])(PackedArgs, ConvGeom);  // [0]: 3 x 3, [1]: any R
 };
 
-#define TG_CONVP(DT, MODE, BM, BN, BK, WGM, WGN, NS)                      \
-    {DT, MODE, BM, BN, BK, NS, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, \
-     &conv3x3_packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
+#define TG_CONVP(DT, MODE, BM, BN, BK, WGM, WGN, NS)                         \
+    {DT, MODE, BM, BN, BK, NS, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT,    \
+     {&conv_packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>, 3>,         \
+      &conv_packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>, 0>}}
 
 // Tile shapes of the packed kernel.  Default (measured over 3x3 layers of
 // 64 to 512 channels and 14 x 14 to 112 x 112 pixels): f32 takes shape 0
@@ -215,11 +237,12 @@ const ConvPacked* conv_packed(int dtype, int i)
 
 struct ConvSched {
     int dtype, BM, BN, vec, threads;
-    void (*kernel)(GemmArgs, ConvGeom);
+    void (*kernel[2])(GemmArgs, ConvGeom);  // [0]: 3 x 3, [1]: any R
 };
 
-#define TG_CONV(DT, MODE, BM, BN, BK, VEC) \
-    {DT, BM, BN, VEC, Cfg<MODE, BM, BN, BK, 2, 2, VEC>::NT, &conv3x3_kernel<Cfg<MODE, BM, BN, BK, 2, 2, VEC>>}
+#define TG_CONV(DT, MODE, BM, BN, BK, VEC)                                      \
+    {DT, BM, BN, VEC, Cfg<MODE, BM, BN, BK, 2, 2, VEC>::NT,                    \
+     {&conv_kernel<Cfg<MODE, BM, BN, BK, 2, 2, VEC>, 3>, &conv_kernel<Cfg<MODE, BM, BN, BK, 2, 2, VEC>, 0>}}
 
 // 128 x 128 tiles for layers with enough output pixels, 64 x 64 otherwise;
 // 16-byte filter loads when Cout and the filter's address allow them.
@@ -237,8 +260,11 @@ const ConvSched kConv[] = {
 namespace tg {
 namespace {
 
+// Kernel variant: 0 = specialised for 3 x 3, 1 = filter size at run time.
+int variant(const ConvGeom& g, bool runtime_r) { return (g.R == 3 && !runtime_r) ? 0 : 1; }
+
 int conv_direct(int64_t M, int64_t Cout, int64_t K, float alpha, const float* X, const float* Wt, float beta,
-                float* Y, int dtype, const ConvGeom& g, hipStream_t s)
+                float* Y, int dtype, const ConvGeom& g, bool runtime_r, hipStream_t s)
 {
     const bool vec = (Cout % 4 == 0) && reinterpret_cast<uintptr_t>(Wt) % 16 == 0;
     const int tile = ((M + 127) / 128) * ((Cout + 127) / 128) >= 192 ? 128 : 64;
@@ -265,7 +291,8 @@ int conv_direct(int64_t M, int64_t Cout, int64_t K, float alpha, const float* X,
     a.group_m = 8;
     a.xcd_remap = 1;
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
-    hipLaunchKernelGGL(pick->kernel, dim3((unsigned)(a.tiles_m * a.tiles_n)), dim3(pick->threads), 0, s, a, g);
+    hipLaunchKernelGGL(pick->kernel[variant(g, runtime_r)], dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                       dim3(pick->threads), 0, s, a, g);
     return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
 }
 
@@ -278,7 +305,8 @@ bool conv_packed_ok(int64_t M, int64_t Cin, int64_t K, int dtype)
 }
 
 int conv_packed_run(const ConvPacked& p, int64_t M, int64_t Cin, int64_t Cout, int64_t K, float alpha,
-                    const float* X, const float* Wt, float beta, float* Y, const ConvGeom& g, hipStream_t s)
+                    const float* X, const float* Wt, float beta, float* Y, const ConvGeom& g, bool runtime_r,
+                    hipStream_t s)
 {
     const int64_t Np = (Cout + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
@@ -315,15 +343,19 @@ int conv_packed_run(const ConvPacked& p, int64_t M, int64_t Cin, int64_t Cout, i
     a.group_m = 8;
     a.xcd_remap = 1;
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
-    hipLaunchKernelGGL(p.kernel, dim3((unsigned)(a.tiles_m * a.tiles_n)), dim3(p.threads), 0, s, a, g);
+    hipLaunchKernelGGL(p.kernel[variant(g, runtime_r)], dim3((unsigned)(a.tiles_m * a.tiles_n)),
+                       dim3(p.threads), 0, s, a, g);
     return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
 }
 
-int conv_run(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha, const float* X,
-             const float* Wt, float beta, float* Y, int dtype, int path, void* stream)
+int conv_run(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, int64_t R, float alpha,
+             const float* X, const float* Wt, float beta, float* Y, int dtype, int path, void* stream)
 {
     if (batch < 0 || H < 0 || W < 0 || Cin < 0 || Cout < 0) return TGEMM_INVALID_VALUE;
+    if (R < 1 || R % 2 == 0 || R > 31) return TGEMM_INVALID_VALUE;
     if (dtype != TGEMM_F32 && dtype != TGEMM_F32_BF16X3) return TGEMM_NOT_SUPPORTED;
+    const bool runtime_r = (path & TGEMM_CONV_RUNTIME_R) != 0;
+    path &= ~TGEMM_CONV_RUNTIME_R;
     const ConvPacked* packed = nullptr;
     if (path >= TGEMM_CONV_PACKED) {
         packed = conv_packed(dtype, path - TGEMM_CONV_PACKED);
@@ -332,11 +364,11 @@ int conv_run(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, flo
         return TGEMM_INVALID_VALUE;
     }
     // the kernels index pixels, k and columns with 32-bit integers
-    if (batch > INT32_MAX || H > INT32_MAX || W > INT32_MAX || Cin > INT32_MAX / 9 || Cout > INT32_MAX)
+    if (batch > INT32_MAX || H > INT32_MAX || W > INT32_MAX || Cin > INT32_MAX / (R * R) || Cout > INT32_MAX)
         return TGEMM_NOT_SUPPORTED;
     const int64_t HW = H * W;
     if (HW > INT32_MAX || (HW > 0 && batch > INT32_MAX / HW)) return TGEMM_NOT_SUPPORTED;
-    const int64_t M = batch * HW, K = 9 * Cin;
+    const int64_t M = batch * HW, K = R * R * Cin;
     if (M == 0 || Cout == 0) return TGEMM_SUCCESS;
     if (!Y) return TGEMM_INVALID_VALUE;
     const bool reads_xw = K > 0 && alpha != 0.f;
@@ -350,16 +382,16 @@ int conv_run(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, flo
     if (!reads_xw)
         return launch_scale_c((int)M, (int)Cout, beta, Y, Cout, s) == hipSuccess ? TGEMM_SUCCESS
                                                                                  : TGEMM_LAUNCH_FAILED;
-    const ConvGeom g{(int)H, (int)W, (int)Cin};
+    const ConvGeom g{(int)H, (int)W, (int)Cin, (int)R};
     const bool packed_ok = conv_packed_ok(M, Cin, K, dtype);
     if (packed && !packed_ok) return TGEMM_NOT_SUPPORTED;
     if (path == TGEMM_CONV_AUTO && packed_ok) packed = conv_packed(dtype, conv_default_shape(dtype, M, Cout));
     if (packed) {
-        rc = conv_packed_run(*packed, M, Cin, Cout, K, alpha, X, Wt, beta, Y, g, s);
+        rc = conv_packed_run(*packed, M, Cin, Cout, K, alpha, X, Wt, beta, Y, g, runtime_r, s);
         // under capture with no workspace yet: the direct kernel needs none
         if (!(rc == TGEMM_CAPTURE_UNPLANNED && path == TGEMM_CONV_AUTO)) return rc;
     }
-    return conv_direct(M, Cout, K, alpha, X, Wt, beta, Y, dtype, g, s);
+    return conv_direct(M, Cout, K, alpha, X, Wt, beta, Y, dtype, g, runtime_r, s);
 }
 
 }  // namespace
@@ -368,14 +400,21 @@ int conv_run(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, flo
 extern "C" int tgemm_conv3x3(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
                              const float* X, const float* Wt, float beta, float* Y, int dtype, void* stream)
 {
-    return tg::conv_run(batch, H, W, Cin, Cout, alpha, X, Wt, beta, Y, dtype, TGEMM_CONV_AUTO, stream);
+    return tg::conv_run(batch, H, W, Cin, Cout, 3, alpha, X, Wt, beta, Y, dtype, TGEMM_CONV_AUTO, stream);
 }
 
 extern "C" int tgemm_conv3x3_path(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, float alpha,
                                   const float* X, const float* Wt, float beta, float* Y, int dtype, int path,
                                   void* stream)
 {
-    return tg::conv_run(batch, H, W, Cin, Cout, alpha, X, Wt, beta, Y, dtype, path, stream);
+    return tg::conv_run(batch, H, W, Cin, Cout, 3, alpha, X, Wt, beta, Y, dtype, path, stream);
+}
+
+extern "C" int tgemm_conv2d(int64_t batch, int64_t H, int64_t W, int64_t Cin, int64_t Cout, int64_t R, float alpha,
+                            const float* X, const float* Wt, float beta, float* Y, int dtype, int path,
+                            void* stream)
+{
+    return tg::conv_run(batch, H, W, Cin, Cout, R, alpha, X, Wt, beta, Y, dtype, path, stream);
 }
 
 extern "C" int tgemm_conv3x3_packed_shape(int dtype, int i, int* bm, int* bn, int* bk, int* stages)

@@ -93,12 +93,12 @@ def grouped_inputs(dims, seed_base=4000):
     return out
 
 
-def conv_layer_inputs(batch, H, W, cin, cout, seed):
-    """X (batch, H, W, cin), Wt (3, 3, cin, cout), Y0 (batch, H, W, cout), U[-1, 1] float32,
+def conv_layer_inputs(batch, H, W, cin, cout, seed, R=3):
+    """X (batch, H, W, cin), Wt (R, R, cin, cout), Y0 (batch, H, W, cout), U[-1, 1] float32,
     drawn in that order from one seeded generator."""
     g = _gen(seed)
     X = uniform(batch * H * W, cin, g).reshape(batch, H, W, cin)
-    Wt = uniform(9 * cin, cout, g).reshape(3, 3, cin, cout)
+    Wt = uniform(R * R * cin, cout, g).reshape(R, R, cin, cout)
     Y0 = uniform(batch * H * W, cout, g).reshape(batch, H, W, cout)
     return X, Wt, Y0
 

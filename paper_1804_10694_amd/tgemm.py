@@ -43,6 +43,7 @@ lib.tgemm_conv3x3_path.argtypes = [_i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _
 lib.tgemm_conv3x3_packed_shape.argtypes = [_i32, _i32, _p, _p, _p, _p]
 lib.tgemm_batched_strided.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _i64, _p, _i64, _i64, _f32, _p, _i64,
                                       _i64, _i32, _p]
+lib.tgemm_conv2d.argtypes = [_i64, _i64, _i64, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _i32, _p]
 lib.tgemm_mfma_loop.argtypes = [_i32, _i64, _p, _i64, _p, _p]
 lib.tgemm_contract.argtypes = [_i32, _p, _p, _p, _i32, _p, _p, _p, _i32, _p, _p, _p, _f32, _f32, _i32, _p]
 lib.tgemm_gemm2.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _i32, _p, _i64, _f32, _p, _i64,
@@ -320,20 +321,24 @@ def conv3x3_packed_shapes(dtype="f32"):
         out.append(tuple(x.value for x in v))
 
 
-def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None, path="auto", shape=0):
-    """3x3 same-padding convolution as an implicit gemm (tgemm_conv3x3):
-    Y = alpha * conv(X, Wt) + beta * Y, with X (batch, H, W, Cin), Wt (3, 3, Cin, Cout)
-    and Y (batch, H, W, Cout) contiguous float32 device tensors.  path "auto" (the
-    library's choice), "direct", or "packed" with tile shape index `shape`
-    (tgemm_conv3x3_path)."""
+CONV_RUNTIME_R = 0x100
+
+
+def conv2d(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None, path="auto", shape=0, runtime_r=False):
+    """R x R same-padding convolution as an implicit gemm (tgemm_conv2d), R = Wt.shape[0] odd:
+    Y = alpha * conv(X, Wt) + beta * Y, with X (batch, H, W, Cin), Wt (R, R, Cin, Cout) and
+    Y (batch, H, W, Cout) contiguous float32 device tensors.  path "auto" (the library's
+    choice), "direct", or "packed" with tile shape index `shape`; runtime_r selects the
+    kernel that takes R at run time also for 3 x 3."""
     import torch
     for name, t in (("X", X), ("Wt", Wt), ("Y", Y)):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
                 or not t.is_contiguous():
             raise TypeError(f"{name} must be a contiguous float32 device tensor")
     nb, H, W, cin = X.shape
-    if tuple(Wt.shape[:3]) != (3, 3, cin) or tuple(Y.shape) != (nb, H, W, Wt.shape[3]):
-        raise ValueError("shapes must be X (b, H, W, Cin), Wt (3, 3, Cin, Cout), Y (b, H, W, Cout)")
+    R = Wt.shape[0]
+    if tuple(Wt.shape[:3]) != (R, R, cin) or tuple(Y.shape) != (nb, H, W, Wt.shape[3]):
+        raise ValueError("shapes must be X (b, H, W, Cin), Wt (R, R, Cin, Cout), Y (b, H, W, Cout)")
     if path == "auto":
         code = CONV_AUTO
     elif path == "direct":
@@ -342,9 +347,18 @@ def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None, path="auto"
         code = CONV_PACKED + int(shape)
     else:
         raise ValueError(f"unknown conv path {path!r}")
-    _check(lib.tgemm_conv3x3_path(nb, H, W, cin, Wt.shape[3], alpha, X.data_ptr(), Wt.data_ptr(), beta,
-                                  Y.data_ptr(), _dtype_code(dtype), code, _stream_handle(stream)),
-           "tgemm_conv3x3_path")
+    if runtime_r:
+        code |= CONV_RUNTIME_R
+    _check(lib.tgemm_conv2d(nb, H, W, cin, Wt.shape[3], R, alpha, X.data_ptr(), Wt.data_ptr(), beta,
+                            Y.data_ptr(), _dtype_code(dtype), code, _stream_handle(stream)), "tgemm_conv2d")
+
+
+def conv3x3(X, Wt, Y, alpha=1.0, beta=0.0, dtype="f32", stream=None, path="auto", shape=0):
+    """3x3 same-padding convolution as an implicit gemm (tgemm_conv3x3_path): conv2d with a
+    3 x 3 x Cin x Cout filter."""
+    if Wt.dim() != 4 or tuple(Wt.shape[:2]) != (3, 3):
+        raise ValueError("conv3x3 takes a (3, 3, Cin, Cout) filter")
+    conv2d(X, Wt, Y, alpha, beta, dtype, stream, path, shape)
 
 
 def set_policy(policy):

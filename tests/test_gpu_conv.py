@@ -171,3 +171,55 @@ def test_graph_replay(tg):
             g.replay()
             torch.cuda.synchronize()
             assert torch.equal(Yg, eager), dt
+
+
+# ---------------------------------------------------------------- R x R filters (tgemm_conv2d)
+def _inputs_r(nb, H, W, cin, cout, R, seed, integer):
+    g = torch.Generator().manual_seed(seed)
+    if integer:
+        mk = lambda *s: torch.randint(-4, 5, s, generator=g).float()      # noqa: E731
+    else:
+        mk = lambda *s: 2 * torch.rand(*s, generator=g) - 1               # noqa: E731
+    return mk(nb, H, W, cin), mk(R, R, cin, cout), mk(nb, H, W, cout)
+
+
+def _run_r(tg, X, Wt, Y0, alpha, beta, dtype, path="auto", shape=0, runtime_r=False):
+    Yd = Y0.clone().to(DEV)
+    tg.conv2d(X.to(DEV), Wt.to(DEV), Yd, alpha, beta, dtype, path=path, shape=shape, runtime_r=runtime_r)
+    torch.cuda.synchronize()
+    return Yd.cpu()
+
+
+@pytest.mark.parametrize("R", [1, 5, 7, 11])
+@pytest.mark.parametrize("kernel", KERNELS[:3], ids=lambda k: f"{k[0]}{k[1]}")
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_rxr_integer_inputs_bit_exact(tg, dtype, kernel, R):
+    # ragged pixel counts (more than one 128-row tile), filter taps reaching past every border
+    for shape in [(2, 9, 13, 8, 20), (1, 17, 15, 16, 130)]:
+        print(f"conv{R}x{R} {dtype} {kernel} {shape}", flush=True)
+        X, Wt, Y0 = _inputs_r(*shape, R, seed=R + sum(shape), integer=True)
+        ref = OC.conv2d(X, Wt, Y0, 1.0, 0.5)
+        got = _run_r(tg, X, Wt, Y0, 1.0, 0.5, dtype, *kernel)
+        np.testing.assert_array_equal(got.numpy().astype(np.float64), ref, err_msg=f"R={R} {dtype} {kernel} {shape}")
+
+
+@pytest.mark.parametrize("kernel", KERNELS[:3], ids=lambda k: f"{k[0]}{k[1]}")
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_3x3_through_the_runtime_r_kernels(tg, dtype, kernel):
+    X, Wt, Y0 = _inputs_r(2, 11, 10, 16, 40, 3, seed=77, integer=True)
+    got = _run_r(tg, X, Wt, Y0, 1.5, 0.5, dtype, *kernel, runtime_r=True)
+    np.testing.assert_array_equal(got.numpy().astype(np.float64), OC.conv2d(X, Wt, Y0, 1.5, 0.5))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_5x5_uniform_within_tolerance(tg, dtype):
+    X, Wt, Y0 = _inputs_r(2, 20, 18, 64, 96, 5, seed=78, integer=False)
+    err = oracle.normwise_error(_run_r(tg, X, Wt, Y0, 1.0, 1.0, dtype).numpy(), OC.conv2d(X, Wt, Y0, 1.0, 1.0))
+    print(f"5x5 {dtype} normwise error {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_even_filter_is_refused(tg):
+    X, _, Y0 = _inputs_r(1, 4, 4, 8, 8, 3, seed=79, integer=True)
+    with pytest.raises(tg.TgemmError):
+        _run_r(tg, X, torch.zeros(4, 4, 8, 8), Y0, 1.0, 0.0, "f32")
