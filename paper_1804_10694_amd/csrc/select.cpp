@@ -165,17 +165,18 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    CU: 138 TFLOP/s at 8192^3 against 122 for the best direct schedule.
     //    Four workgroups per CU run as fast but re-read 2.6 times the HBM
     //    bytes (more tiles in flight drift apart in K and share the L2 less);
-    //  - e4m3: 128 x 128 macro-tiles, two 32 KB stages, four workgroups per
-    //    CU: 1120 TFLOP/s at 16384^3 against 1030 for 256 x 256 tiles (the
-    //    extra workgroups keep more panel loads in flight);
-    //  - x3 and bf16: 256 x 256 macro-tiles of 8 waves, down to half a wave
-    //    of tiles (one workgroup per CU still beats 128 x 128 tiles there).
+    //  - x3, bf16 and e4m3: 256 x 256 macro-tiles of 8 waves, down to half a
+    //    wave of tiles (one workgroup per CU still beats 128 x 128 tiles
+    //    there); e4m3 with 128-deep panels, 1295 TFLOP/s at 16384^3 against
+    //    1195 for 128 x 128 tiles of four workgroups per CU (which it takes
+    //    below that size).
     if (K >= 512 && packed_k_ok(K, dtype)) {
         int id = -1;
         if (dtype == TGEMM_F32) {
             if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
         } else if (dtype == TGEMM_FP8_E4M3) {
-            if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, 0, 2, 2, 32768);
+            if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, 128, 0, 2, 4);
+            else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, 0, 2, 2, 32768);
         } else {
             const int bk = dtype == TGEMM_F32_BF16X3 ? 32 : 64;
             if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, bk, 0, 2, 4);

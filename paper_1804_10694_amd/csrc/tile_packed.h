@@ -587,8 +587,27 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     constexpr int NS = CF::NS, L = AL::LOADS + BL::LOADS;
     static_assert((NS - 2) * L <= 63, "vmcnt holds at most 63");
     for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
+    // Scaled forms: acc is kept divided by the scale product of the current K
+    // block (128 deep).  The products of the next block are loaded one panel
+    // ahead, before that panel's successor is issued, so the waits of the panel
+    // pipeline cover them; loading them where they are used would drain the
+    // panels in flight at every block boundary.  (They are vector loads: C is
+    // written by the same kernel and may alias the scales.)
     int kb_cur = 0;
-    // new K scale block at panel s: keep acc divided by the current scale product
+    float sc_cur[CF::TM][CF::TN], sc_next[CF::TM][CF::TN];
+    auto load_scales = [&](int kb, float (&dst)[CF::TM][CF::TN]) {
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
+    };
+    if (scaled) load_scales(0, sc_cur);
+    auto prefetch = [&](int s) {  // during panel s: the scales of panel s + 1 if it opens a block
+        if (!scaled || s + 1 >= npanel) return;
+        const int kb = ((s + 1) * CF::BK) / 128;
+        if (kb != (s * CF::BK) / 128) load_scales(kb, sc_next);
+    };
+    // new K scale block at panel s: move acc to the new block's scale product
     auto rescale = [&](int s) {
         if (!scaled) return;
         const int kb = (s * CF::BK) / 128;
@@ -597,10 +616,10 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j) {
-                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
-                const float ratio = block_scale(a, r0, c0, kb_cur) / block_scale(a, r0, c0, kb);
+                const float ratio = sc_cur[i][j] / sc_next[i][j];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                sc_cur[i][j] = sc_next[i][j];
             }
         kb_cur = kb;
     };
@@ -612,8 +631,9 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
             if (s + NS - 2 < npanel) wait_vmcnt<(NS - 2) * L>();
             else wait_vmcnt<0>();
             lds_barrier();
+            rescale(s);   // consumes the scales prefetched during panel s - 1 ...
+            prefetch(s);  // ... before they are replaced by those of panel s + 1
             if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
-            rescale(s);
             pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
         }
     } else {
@@ -631,8 +651,9 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         lds_barrier();
         OP::load(lds, ops[0], 0, wm0, wn0, lane);
         for (int s = 0; s < npanel; ++s) {
-            if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
             rescale(s);
+            prefetch(s);
+            if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
             const char* stage = lds + (s % NS) * CF::LDS_STAGE;
 #pragma unroll
             for (int g = 0; g < CF::NG; ++g) {
@@ -669,7 +690,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j) {
             const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
-            const float sc = a.alpha * (scaled ? block_scale(a, r0, c0, kb_cur) : 1.f);
+            const float sc = a.alpha * (scaled ? sc_cur[i][j] : 1.f);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
