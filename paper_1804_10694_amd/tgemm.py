@@ -21,7 +21,7 @@ SUCCESS, INVALID_VALUE, NOT_SUPPORTED, LAUNCH_FAILED = 0, 1, 2, 3
 ALLOC_FAILED, CAPTURE_UNPLANNED, INTERNAL, NO_DEVICE = 4, 5, 6, 7
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1804_10694_amd.build first")
 
 lib = ctypes.CDLL(LIB_PATH)
 _i64, _i32, _f32, _p = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_void_p
