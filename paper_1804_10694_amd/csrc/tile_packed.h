@@ -458,14 +458,21 @@ struct PackedOps {
 // MFMAs over one LDS stage.  Operand registers are double-buffered: the reads
 // of group g + 1 are issued before the MFMAs of group g, and the scheduler is
 // asked to interleave them, so LDS latency hides behind the matrix unit.
-template <class CF, class OP = PackedOps<CF>>
+struct NoIssue {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// `then` runs after the first group's LDS reads are issued (the caller issues
+// the next panel's loads there, so the reads do not queue behind them).
+template <class CF, class OP = PackedOps<CF>, class F = NoIssue>
 __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
-                                       int wn0, int lane)
+                                       int wn0, int lane, const F& then = F())
 {
     constexpr int NREAD = OP::NREAD;
     constexpr int NMFMA = OP::NMFMA;
     typename OP::Ops ops[2];
     OP::load(stage, ops[0], 0, wm0, wn0, lane);
+    then();
 #pragma unroll
     for (int g = 0; g < CF::NG; ++g) {
         if (g + 1 < CF::NG) OP::load(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
@@ -481,9 +488,9 @@ __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][
     }
 }
 
-// Scale product of block (row0, col0) for K scale block kb.
-// (row0, col0 and kb are wave-uniform, so the two loads are scalar loads and do
-// not count against vmcnt, which tracks the panel pipeline.)
+// Scale product of block (row0, col0) for K scale block kb.  (The loads are
+// vector loads, counted by vmcnt like the panel loads: packed_tile issues
+// them one panel ahead of their use.)
 __device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int col0, int kb)
 {
     if (row0 >= a.M || col0 >= a.N) return 1.f;  // a block of padding: never stored
@@ -633,8 +640,18 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
             lds_barrier();
             rescale(s);   // consumes the scales prefetched during panel s - 1 ...
             prefetch(s);  // ... before they are replaced by those of panel s + 1
-            if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
-            pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+            // On 256 x 256 tiles the next panel's loads go out after the first group of
+            // LDS reads, which then do not wait behind them; on smaller tiles, with
+            // fewer MFMAs per panel to cover the loads, they go out first.
+            auto next = [&] {
+                if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
+            };
+            if constexpr (CF::BM >= 256 && CF::BN >= 256) {
+                pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane, next);
+            } else {
+                next();
+                pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+            }
         }
     } else {
         // Three or more stages: the next panel has landed before this one ends, so
