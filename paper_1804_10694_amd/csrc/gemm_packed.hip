@@ -77,6 +77,8 @@ const PSched kPacked[] = {
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 16, 2, 2, 3),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 128, 32, 2, 2, 3),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 128, 64, 2, 2, 3),
+    // two workgroups per CU of 8 waves, each wave 32 x 128 of the tile
+    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 256, 16, 4, 2, 3),
     // one workgroup per CU, 8 waves
     TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 32, 2, 4, 2),
     TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 16, 2, 4, 4),
@@ -88,6 +90,7 @@ const PSched kPacked[] = {
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 32, 2, 4, 4),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 64, 2, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 2, 4, 2),
+    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 4, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 64, 2, 4, 4),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2, 2),
 };

@@ -161,21 +161,25 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     };
     // Large problems take packed operands (the packing pass costs O(MK + KN)
     // against O(MNK)).  Measured on MI355X:
-    //  - f32: 128 x 128 macro-tiles, four 16 KB LDS stages, two workgroups per
-    //    CU: 138 TFLOP/s at 8192^3 against 122 for the best direct schedule.
-    //    Four workgroups per CU run as fast but re-read 2.6 times the HBM
-    //    bytes (more tiles in flight drift apart in K and share the L2 less);
+    //  - f32: 128 x 256 macro-tiles of 8 waves (4 x 2, each wave 32 x 128),
+    //    three 24 KB LDS stages, two workgroups per CU: 144 TFLOP/s at 8192^3
+    //    and 91 at 4097 x 3001 x 2053, against 136 and 83 for 128 x 128 tiles
+    //    of 4 waves (64 x 64 each) on the same GPU, and 122 for the best
+    //    direct schedule.  The transposed wave shape (128 x 32) gains nothing.
+    //    Smaller problems keep the 128 x 128 tiles;
     //  - x3, bf16 and e4m3: 256 x 256 macro-tiles of 8 waves, down to half a
     //    wave of tiles (one workgroup per CU still beats 128 x 128 tiles
-    //    there); e4m3 with 128-deep panels, 1295 TFLOP/s at 16384^3 against
+    //    there); e4m3 with 128-deep panels and its waves 4 x 2 (64 x 128
+    //    each), 1317 TFLOP/s at 16384^3 against 1266 with waves 2 x 4 and
     //    1195 for 128 x 128 tiles of four workgroups per CU (which it takes
     //    below that size).
     if (K >= 512 && packed_k_ok(K, dtype)) {
         int id = -1;
         if (dtype == TGEMM_F32) {
-            if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
+            if (tiles(128, 256) >= 256) id = find_schedule(dtype, 128, 256, 16, 0, 4, 2);
+            else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
         } else if (dtype == TGEMM_FP8_E4M3) {
-            if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, 128, 0, 2, 4);
+            if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, 128, 0, 4, 2);
             else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, 0, 2, 2, 32768);
         } else {
             const int bk = dtype == TGEMM_F32_BF16X3 ? 32 : 64;
