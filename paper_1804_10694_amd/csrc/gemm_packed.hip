@@ -3,8 +3,8 @@
 // (pack_rows_kernel for A, pack_cols_kernel for B^T) fills a workspace owned
 // by the library per (device, stream); the main kernel runs one macro-tile per
 // workgroup with the pipeline of tile_packed.h.  Packed rows are padded to
-// multiples of kPackRows and K to a multiple of kPackK, so every schedule of
-// the table reads whole tiles and whole panels.
+// multiples of kPackRows and K to a multiple of kPackK (packed_kp), so every
+// schedule of the table reads whole tiles and whole panels.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -131,8 +131,8 @@ size_t packed_workspace_bytes(int64_t M, int64_t N, int64_t K, int dtype)
 {
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
-    const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
     const int64_t es = dtype == TGEMM_FP8_E4M3 ? 1 : dtype == TGEMM_F32 ? 4 : 2;
+    const int64_t Kp = packed_kp(K, es);
     const int64_t arrays = dtype == TGEMM_F32_BF16X3 ? 2 : 1;
     return (size_t)((Mp + Np) * Kp * es * arrays);
 }
@@ -232,9 +232,8 @@ int launch_pack_cols(int mode, const void* X, int64_t ldx, int64_t K, int64_t N,
 // Pack A and B into `ws` and run packed schedule `pid` (index into kPacked).
 bool packed_k_ok(int64_t K, int dtype)
 {
-    const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
     const int64_t es = dtype == TGEMM_FP8_E4M3 ? 1 : dtype == TGEMM_F32 ? 4 : 2;
-    return kPackRows * Kp * es <= INT32_MAX;
+    return kPackRows * packed_kp(K, es) * es <= INT32_MAX;
 }
 
 int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
@@ -245,8 +244,8 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     if (!packed_k_ok(K, p.dtype)) return TGEMM_NOT_SUPPORTED;
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
-    const int64_t Kp = (K + kPackK - 1) / kPackK * kPackK;
     const int64_t es = p.dtype == TGEMM_FP8_E4M3 ? 1 : p.dtype == TGEMM_F32 ? 4 : 2;
+    const int64_t Kp = packed_kp(K, es);
     char* base = static_cast<char*>(ws);
     char* Ap = base;
     char* Alo = p.mode == MODE_X3 ? Ap + Mp * Kp * es : nullptr;

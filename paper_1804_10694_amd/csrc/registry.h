@@ -53,6 +53,17 @@ int launch_pack_cols(int mode, const void* X, int64_t ldx, int64_t K, int64_t N,
                      int64_t Np, int64_t Kp, hipStream_t s);
 constexpr int kPackRows = 256;  // packed row counts of the gemm path are multiples of this
 constexpr int kPackK = 128;     // packed K of the gemm path is a multiple of this (elements)
+// Packed row length (elements) of the gemm path for K and an element size of
+// es bytes: K rounded up to kPackK, plus 512 bytes when that row pitch is a
+// multiple of 4 KB.  With such a pitch the panel loads of all workgroups at
+// one K position fall on the same few memory channels; the pad spreads them
+// (measured on MI355X: x3 at 8192^3 +3%, e4m3 at 16384^3 +2%, bf16 even;
+// pads of 128 or 256 bytes were slower for some of them).
+constexpr int64_t packed_kp(int64_t K, int64_t es)
+{
+    const int64_t kp = (K + kPackK - 1) / kPackK * kPackK;
+    return (kp * es) % 4096 == 0 ? kp + 512 / es : kp;
+}
 // Position of a schedule id inside packed_schedules(), or -1.
 int packed_index(int id);
 
