@@ -110,6 +110,21 @@ def test_packed_schedules_exact_with_vector_packing(tg, dtype):
                                           err_msg=f"schedule {sid} {info} {(M, N, K)}")
 
 
+@pytest.mark.parametrize("dtype,K", [("f32", 1024), ("x3", 2048)])
+def test_packed_schedules_exact_padded_row_pitch(tg, dtype, K):
+    # K * element size a multiple of 4 KB: the packed rows get 512 bytes of padding past K,
+    # so every panel load runs on the padded pitch; ragged M and N, NaN canaries around C
+    M, N = 300, 270
+    A, B, C0 = inputs.integer_inputs(M, N, K, seed=40 + K)
+    ref = oracle.gemm(A, B, C0, 1.0, 0.5)
+    for sid, info in _serving(tg, dtype, vec=0):
+        print(f"packed schedule {sid} {info} M={M} N={N} K={K}", flush=True)
+        got, ok = _run(tg, A, B, C0, 1.0, 0.5, dtype, sid, ld_pad="align4")
+        assert ok, f"canary overwritten by schedule {sid}"
+        np.testing.assert_array_equal(got.numpy().astype(np.float64), ref,
+                                      err_msg=f"schedule {sid} {info} {(M, N, K)}")
+
+
 def test_brute_force_tiny_sizes(tg):
     # All small (M, N) with a ladder of K values, default policy, integer inputs.
     Ks = [1, 2, 3, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129]

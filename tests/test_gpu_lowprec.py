@@ -163,6 +163,33 @@ def test_packed_schedules_scaled_exact(tg, dtype):
         tg.set_policy("default")
 
 
+@pytest.mark.parametrize("dtype,K", [("bf16", 2048), ("fp8", 4096)])
+def test_packed_schedules_scaled_exact_padded_row_pitch(tg, dtype, K):
+    # K * element size a multiple of 4 KB: the packed rows get 512 bytes of padding past K;
+    # integer codes, power-of-two scales changing across K blocks, every packed schedule exact
+    M, N = 300, 270
+    A, B, _ = inputs.integer_inputs(M, N, K, seed=41 + K, r=8)
+    g = np.random.default_rng(42)
+    SA = (2.0 ** g.integers(-2, 3, P.scale_grid_shape(M, K))).astype(np.float32)
+    SB = (2.0 ** g.integers(-2, 3, P.scale_grid_shape(K, N))).astype(np.float32)
+    if dtype == "fp8":
+        QA, QB = P.e4m3_encode(A.numpy().astype(np.float64)), P.e4m3_encode(B.numpy().astype(np.float64))
+    else:
+        QA, QB = P.bf16_bits(A.numpy()), P.bf16_bits(B.numpy())
+    C0 = np.random.default_rng(43).integers(-4, 5, (M, N)).astype(np.float32)
+    ref = P.gemm_scaled_expected(QA, SA, QB, SB, C0, 1.0, 0.5, dtype)
+    packed = [sid for sid, info in tg.schedules(dtype) if info["vec"] == 0]
+    assert packed
+    try:
+        for sid in packed:
+            print(f"packed schedule {sid} {dtype} K={K}", flush=True)
+            tg.set_policy(f"force:{sid}")
+            got = _gemm_scaled(tg, QA, SA, QB, SB, C0, 1.0, 0.5, dtype)
+            np.testing.assert_array_equal(got.astype(np.float64), ref, err_msg=f"schedule {sid}")
+    finally:
+        tg.set_policy("default")
+
+
 # ------------------------------------------------------------------ tolerance
 @pytest.mark.parametrize("dtype", ["bf16", "fp8"])
 @pytest.mark.parametrize("shape", [(512, 512, 1024), (300, 389, 517)])
