@@ -633,14 +633,15 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
             }
         kb_cur = kb;
     };
-    if constexpr (NS == 2 && (CF::MODE == MODE_FP8 || CF::NG == 1)) {
+    if constexpr (NS == 2 && (CF::MODE == MODE_FP8 || (CF::NG == 1 && CF::BM >= 128))) {
         // Two stages, refilled early: panel s + 2 goes into panel s's stage as
         // soon as every wave holds the operands of its last group of panel s (a
         // barrier before that group's MFMAs), so its loads have the rest of panel
         // s and all of panel s + 1 to land, at one more barrier per panel.
-        // Measured on MI355X: e4m3 +4-6%, one-group panels (x3 128x128x16) twice
-        // as fast; bf16 with four groups per panel 11% slower, so the others keep
-        // the loop below.
+        // Measured on MI355X: e4m3 +4-6%, one-group panels of 128-row tiles (x3
+        // 128x128x16) twice as fast; bf16 with four groups per panel 11% slower
+        // and the 64 x 64 in-place x3 tiles of the grouped launch about 5%, so
+        // the others keep the loop below.
         static_assert(L <= 63, "vmcnt holds at most 63");
         if (1 < npanel) issue(1, lds + CF::LDS_STAGE);
         for (int s = 0; s < npanel; ++s) {
