@@ -8,7 +8,7 @@
  * gemm: two-level tiling (Sections I and VI-A), array packing into a staging
  * buffer (Section I; here the LDS), register blocking (Sections I and VI-A;
  * here MFMA accumulator tiles), separation of full tiles from partial tiles
- * (Section V-C, code generation: full tiles take an unpredicated body, partial
+ * (Section V-A, code generation: full tiles take an unpredicated body, partial
  * tiles a predicated one, so no thread diverges), and tile sizes chosen by
  * measurement (Section VI-A, autotuning).
  *
@@ -30,6 +30,12 @@
  *     the caller's next synchronisation, not here.
  *   - Calls are thread-safe; overlapping calls on one stream are ordered by
  *     the stream, calls on different streams that write the same C race.
+ *   - Workspaces the library owns (packing buffers, contraction copies) are
+ *     per (device, stream).  One outgrown by a later, larger call is retired,
+ *     not freed, and every buffer is kept until tgemm_shutdown(), so a HIP
+ *     graph captured over a call stays valid after later eager calls.  Such a
+ *     graph writes the workspace of the stream it was captured on: replaying
+ *     it on another stream while calls run on the capture stream races.
  */
 #ifndef TGEMM_H
 #define TGEMM_H
@@ -58,7 +64,9 @@ typedef enum {
     TGEMM_ALLOC_FAILED = 4,     /* device memory for a plan could not be allocated */
     TGEMM_CAPTURE_UNPLANNED = 5,/* batched call under stream capture with no plan  */
     TGEMM_INTERNAL = 6,
-    TGEMM_NO_DEVICE = 7         /* no usable gfx950 device                         */
+    TGEMM_NO_DEVICE = 7,        /* no usable gfx950 device                         */
+    TGEMM_SCRATCH_TOO_SMALL = 8 /* tgemm_noalloc: the problem's workspace exceeds
+                                   TGEMM_NOALLOC_SCRATCH_BYTES                      */
 } tgemm_status;
 
 /*
@@ -71,6 +79,34 @@ typedef enum {
 int tgemm(int64_t M, int64_t N, int64_t K, float alpha,
           const void* A, int64_t lda, const void* B, int64_t ldb,
           float beta, float* C, int64_t ldc, int dtype, void* stream);
+
+/* Size of the static device array that tgemm_noalloc uses as its workspace. */
+#define TGEMM_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/*
+ * tgemm that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Arguments, results and degenerate cases as tgemm, with the
+ * same schedule choice except that the cost model is never run (its cached
+ * answers, the tuning database and the built-in rule are used).  A packed
+ * schedule's packing workspace is a static device array of
+ * TGEMM_NOALLOC_SCRATCH_BYTES (128 MiB) in the library's code object, one per
+ * device, held from the library's first use on that device until the process
+ * ends; its device address is looked up once per device, on the first call.
+ * No hipMalloc, hipFree or allocating library routine is called.
+ * Workspace need of a packed schedule: (Mp + Np) * Kp * e bytes with Mp, Np
+ * the sizes rounded up to 256, Kp = K rounded up to 128 (plus 512 bytes per
+ * row when that row is a multiple of 4 KB), e = 4 for F32 and
+ * F32_BF16X3, 2 for BF16, 1 for FP8_E4M3: 4096 x 4096 x 2048 fits in every
+ * form; larger packed problems return TGEMM_SCRATCH_TOO_SMALL before any
+ * launch.  Every call on a device shares that device's array: calls that may
+ * overlap on one device (different streams, or threads without ordering)
+ * race, and must be serialised by the caller.  Each call writes every byte of
+ * the region it reads before reading it, so no clearing is needed.
+ */
+int tgemm_noalloc(int64_t M, int64_t N, int64_t K, float alpha,
+                  const void* A, int64_t lda, const void* B, int64_t ldb,
+                  float beta, float* C, int64_t ldc, int dtype, void* stream);
 
 /*
  * Same as tgemm with an explicit schedule id (see tgemm_schedule_count /
@@ -123,8 +159,9 @@ int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx
  * (project addition).  Every array argument is a HOST array of length count;
  * the matrix pointers in them are device pointers.  The first call for a new
  * problem set (dimensions, leading dimensions, pointers, alpha, beta, dtype)
- * chooses a schedule per problem, builds the tile index space and uploads a
- * descriptor table to device memory owned by the library; later calls with
+ * assigns each problem a tile class by the set's plan shape (below), builds
+ * the tile index space and uploads a descriptor table to device memory owned
+ * by the library; later calls with
  * the same set launch at most three kernels (packing pass, packed-class
  * tiles, direct-class tiles; see tgemm_batched_with_shape for the two
  * classes).  The plan shape is what tgemm_batched_autotune measured for sets
@@ -354,7 +391,7 @@ int tgemm_schedule_info(int schedule_id, int* info);
 
 /*
  * Tile placement of one launch, computed on the host exactly as the kernels
- * compute it (no HIP call; used to check the tiling map of Section V-A is a
+ * compute it (no HIP call; used to check that the tiling map of Sections III-C and V is a
  * bijection).  For workgroup w in [0, tiles_m*tiles_n) it writes tile_m[w],
  * tile_n[w] and full[w] (1 when the tile lies inside M x N).
  */

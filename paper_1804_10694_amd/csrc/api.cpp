@@ -170,6 +170,7 @@ const char* tgemm_status_string(int status)
         case TGEMM_CAPTURE_UNPLANNED: return "TGEMM_CAPTURE_UNPLANNED";
         case TGEMM_INTERNAL: return "TGEMM_INTERNAL";
         case TGEMM_NO_DEVICE: return "TGEMM_NO_DEVICE";
+        case TGEMM_SCRATCH_TOO_SMALL: return "TGEMM_SCRATCH_TOO_SMALL";
         default: return "TGEMM_UNKNOWN_STATUS";
     }
 }

@@ -66,10 +66,13 @@ namespace {
 
 unsigned grid_for(int64_t total) { return (unsigned)std::min<int64_t>((total + 255) / 256, 8192); }
 
-// Per (device, stream) workspace of the canonical copies, grown on demand.
+// Per (device, stream) workspace of the canonical copies, grown on demand.  An
+// outgrown buffer is retired, not freed (a graph captured over an earlier call
+// still uses it), and freed at shutdown.
 struct CtWorkspace {
     void* ptr = nullptr;
     size_t bytes = 0;
+    std::vector<void*> retired;
 };
 std::mutex g_ct_mu;
 std::map<std::pair<int, hipStream_t>, CtWorkspace> g_ct_ws;
@@ -84,10 +87,10 @@ int ct_workspace(hipStream_t s, size_t bytes, void** out)
         hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
             return TGEMM_CAPTURE_UNPLANNED;
-        if (w.ptr) (void)hipFree(w.ptr);
-        w.ptr = nullptr;
-        w.bytes = 0;
-        if (hipMalloc(&w.ptr, bytes) != hipSuccess) return TGEMM_ALLOC_FAILED;
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return TGEMM_ALLOC_FAILED;
+        if (w.ptr) w.retired.push_back(w.ptr);
+        w.ptr = p;
         w.bytes = bytes;
     }
     *out = w.ptr;
@@ -154,8 +157,10 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 void contract_shutdown()
 {
     std::lock_guard<std::mutex> lk(g_ct_mu);
-    for (auto& kv : g_ct_ws)
+    for (auto& kv : g_ct_ws) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        for (void* p : kv.second.retired) (void)hipFree(p);
+    }
     g_ct_ws.clear();
 }
 

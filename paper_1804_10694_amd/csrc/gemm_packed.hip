@@ -10,14 +10,28 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "../../include/tgemm.h"
 #include "kargs.h"
 #include "registry.h"
+#include "select.h"
 #include "tile_f32x3.h"
 #include "tile_packed.h"
 
 namespace tg {
+
+// Host helpers of api.cpp (argument checks, device check, launches).
+int validate_gemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+                  const void* B, int64_t ldb, float beta, const float* C, int64_t ldc, int dtype);
+int ensure_device(hipStream_t stream);
+bool vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int dtype);
+int run_gemm(int id, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+             const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int group_m,
+             int xcd_remap, hipStream_t stream);
+int run_scaled(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+               const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
+               int64_t ldc, int dtype, int id, int group_m, int xcd_remap, hipStream_t s);
 
 // ------------------------------------------------------------------ kernels
 // Groups of 8 k are numbered row by row; fewer than 2^32 of them (checked on
@@ -110,13 +124,26 @@ struct DescInit {
     }
 } g_desc_init;
 
-// Per (device, stream) packing workspace, grown on demand, freed at shutdown.
+// Per (device, stream) packing workspace, grown on demand.  A buffer that is
+// outgrown is retired, not freed: a HIP graph captured over an earlier call
+// still holds its address and writes into it on every replay.  Retired
+// buffers are freed at shutdown (or when their stream's workspace is released).
 struct Workspace {
     void* ptr = nullptr;
     size_t bytes = 0;
+    std::vector<void*> retired;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+void free_workspace(Workspace& w)
+{
+    if (w.ptr) (void)hipFree(w.ptr);
+    for (void* p : w.retired) (void)hipFree(p);
+    w.ptr = nullptr;
+    w.bytes = 0;
+    w.retired.clear();
+}
 
 }  // namespace
 
@@ -147,16 +174,17 @@ int packed_workspace(hipStream_t s, size_t bytes, void** out)
         hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
             return TGEMM_CAPTURE_UNPLANNED;  // allocation is not allowed under capture
-        if (w.ptr) (void)hipFree(w.ptr);
-        w.ptr = nullptr;
-        w.bytes = 0;
-        if (hipMalloc(&w.ptr, bytes) != hipSuccess) return TGEMM_ALLOC_FAILED;
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return TGEMM_ALLOC_FAILED;
+        if (w.ptr) w.retired.push_back(w.ptr);
+        w.ptr = p;
         w.bytes = bytes;
     }
     *out = w.ptr;
     return TGEMM_SUCCESS;
 }
 
+// Only for streams whose calls were never captured (the autotuner's own stream).
 void packed_release(hipStream_t s)
 {
     int dev = 0;
@@ -164,15 +192,14 @@ void packed_release(hipStream_t s)
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_pair(dev, s));
     if (it == g_ws.end()) return;
-    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    free_workspace(it->second);
     g_ws.erase(it);
 }
 
 void packed_shutdown()
 {
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    for (auto& kv : g_ws)
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    for (auto& kv : g_ws) free_workspace(kv.second);
     g_ws.clear();
 }
 
@@ -281,6 +308,34 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
 }
 
+// ------------------------------------------------- no-allocation entry point
+// Packing workspace of tgemm_noalloc: one static array per device, part of the
+// library's code object, so it exists from the moment the library is loaded on
+// a device until the process ends.  Host code never passes `scratch` itself to
+// a kernel (in host code the name is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device, on the first
+// call made with that device current.
+static __device__ __align__(256) char scratch[TGEMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];  // device address of `scratch`, per device id
+
+int scratch_address(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TGEMM_NO_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TGEMM_LAUNCH_FAILED;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TGEMM_SUCCESS;
+}
+}  // namespace
+
 int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
                const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                int64_t ldc, int group_m, int xcd_remap, hipStream_t s)
@@ -294,3 +349,39 @@ int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void
 }
 
 }  // namespace tg
+
+// tgemm without any allocation (declared in include/tgemm.h).
+extern "C" int tgemm_noalloc(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+                             const void* B, int64_t ldb, float beta, float* C, int64_t ldc, int dtype,
+                             void* stream)
+{
+    using namespace tg;
+    int rc = validate_gemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+    if (rc != TGEMM_SUCCESS) return rc;
+    if (M == 0 || N == 0) return TGEMM_SUCCESS;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = ensure_device(s)) != TGEMM_SUCCESS) return rc;
+    if (K == 0 || alpha == 0.f)
+        return launch_scale_c((int)M, (int)N, beta, C, ldc, s) == hipSuccess ? TGEMM_SUCCESS
+                                                                             : TGEMM_LAUNCH_FAILED;
+    // the cost model is never run here (a new prediction runs, and may allocate for, the
+    // network); its cached answers, the tuning database and the rule are
+    Choice ch;
+    const bool vok = vec_ok(A, lda, B, ldb, dtype);
+    if ((rc = select_schedule(M, N, K, dtype, vok, &ch, false)) != TGEMM_SUCCESS) return rc;
+    const bool scaled = (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3);
+    const int pid = packed_index(ch.id);
+    if (pid < 0) {  // direct schedules use no workspace
+        if (scaled)
+            return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype, ch.id,
+                              ch.group_m, ch.xcd_remap, s);
+        return run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m, ch.xcd_remap, s);
+    }
+    if (!packed_k_ok(K, dtype)) return TGEMM_NOT_SUPPORTED;
+    if (packed_workspace_bytes(M, N, K, dtype) > (size_t)TGEMM_NOALLOC_SCRATCH_BYTES)
+        return TGEMM_SCRATCH_TOO_SMALL;
+    void* ws = nullptr;
+    if ((rc = scratch_address(&ws)) != TGEMM_SUCCESS) return rc;
+    return run_packed_ws(pid, M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, ch.group_m,
+                         ch.xcd_remap, ws, s);
+}

@@ -32,7 +32,8 @@ struct TileCoord {
     int tm, tn;
 };
 
-// Tiling map of the Tiramisu paper, Section V-A (i0 = floor(i/T), i1 = i % T
+// Tiling map of the Tiramisu paper (the map of a tiling command, Section III-C,
+// as the introduction of Section V writes it: i0 = floor(i/T), i1 = i % T
 // in each dimension): workgroup `wg` owns macro-tile (tm, tn) and computes rows
 // [tm*BM, tm*BM+BM) x columns [tn*BN, tn*BN+BN).  The order in which tiles are
 // handed out is a bijection of [0, tiles_m*tiles_n) built from two steps:

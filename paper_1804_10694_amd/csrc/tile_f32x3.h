@@ -12,7 +12,7 @@
 // barrier per panel swaps the two LDS stages (Layer IV synchronisation,
 // Section IV).  Tiles that lie wholly inside M x N run an unpredicated body;
 // the others run a predicated body (full/partial tile separation,
-// Section V-C); the choice is uniform per workgroup, so no wave diverges.
+// Section V-A); the choice is uniform per workgroup, so no wave diverges.
 //
 // Packing layout.  LDS holds 16-byte "units": KU consecutive k values of one
 // row of A (or one column of B).  F32: KU = 4 floats; X3: KU = 8 bf16, kept in

@@ -10,7 +10,7 @@
 // where conv is the x3 split (two arrays, hi and lo) or a plain copy of the
 // values (f32) or codes (bf16, e4m3).  Rows are padded to whole macro-tiles
 // and K to whole panels, with zeros, so the main loop's loads carry no
-// predicates; full/partial tiles (Section V-C) differ only in the epilogue.
+// predicates; full/partial tiles (Section V-A) differ only in the epilogue.
 //
 // Main loop: K panels of BK go from the packed buffers straight into LDS with
 // buffer_load ... lds (16 bytes per lane, no register staging); NS stages,

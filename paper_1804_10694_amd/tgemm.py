@@ -19,6 +19,8 @@ DTYPES = {"f32": F32, "x3": F32_BF16X3, "bf16": BF16, "fp8": FP8_E4M3}
 
 SUCCESS, INVALID_VALUE, NOT_SUPPORTED, LAUNCH_FAILED = 0, 1, 2, 3
 ALLOC_FAILED, CAPTURE_UNPLANNED, INTERNAL, NO_DEVICE = 4, 5, 6, 7
+SCRATCH_TOO_SMALL = 8
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1804_10694_amd.build first")
@@ -31,6 +33,7 @@ _pf32 = ctypes.POINTER(ctypes.c_float)
 _pp = ctypes.POINTER(ctypes.c_void_p)
 
 lib.tgemm.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _f32, _p, _i64, _i32, _p]
+lib.tgemm_noalloc.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _f32, _p, _i64, _i32, _p]
 lib.tgemm_with_schedule.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _f32, _p, _i64,
                                     _i32, _i32, _i32, _i32, _p]
 lib.tgemm_scaled.argtypes = [_i64, _i64, _i64, _f32, _p, _i64, _p, _p, _i64, _p, _f32, _p, _i64,
@@ -149,6 +152,21 @@ def gemm(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None):
     pc, ldc = _mat(C, "C", torch.float32)
     _check(lib.tgemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dt, _stream_handle(stream)),
            "tgemm")
+    return C
+
+
+def gemm_noalloc(A, B, C, alpha=1.0, beta=0.0, dtype="f32", stream=None):
+    """C = alpha*A@B + beta*C in place without any device allocation (tgemm_noalloc)."""
+    dt = _dtype_code(dtype)
+    M, K = A.shape
+    N = B.shape[1]
+    if B.shape[0] != K or tuple(C.shape) != (M, N):
+        raise ValueError(f"shape mismatch {tuple(A.shape)} @ {tuple(B.shape)} -> {tuple(C.shape)}")
+    pa, lda = _mat(A, "A", _ELEM.get(dt))
+    pb, ldb = _mat(B, "B", _ELEM.get(dt))
+    pc, ldc = _mat(C, "C", torch.float32)
+    _check(lib.tgemm_noalloc(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, dt, _stream_handle(stream)),
+           "tgemm_noalloc")
     return C
 
 

@@ -2,8 +2,9 @@
 
 The library loads and exports every function include/tgemm.h declares;
 argument validation answers before any HIP call; the host tile planner is the
-bijection the tiling map of the Tiramisu paper (Section V-A) describes, and
-classifies full and partial tiles as Section V-C defines them.
+bijection the tiling map of the Tiramisu paper describes (the map a tiling
+command of Section III-C becomes, given in the introduction of Section V), and
+classifies full and partial tiles as Section V-A (code generation) defines them.
 """
 import ctypes
 import os

@@ -153,7 +153,7 @@ def test_inplace_tiles_uniform_inputs(tg, dtype, dims):
         assert oracle.normwise_error(g.numpy(), ref) <= 1e-5, f"problem {p} {dims[p]}"
 
 
-@pytest.mark.parametrize("shape", [None, {"threshold": 96, "large": NEVER}], ids=["default", "direct"])
+@pytest.mark.parametrize("shape", [None, {"threshold": NEVER, "large": NEVER}], ids=["default", "inplace-64"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_grouped_config_512_problems(tg, dtype, shape):
     # 512 problems, M, N, K log-uniform in [16, 2048] (seed 4), matrices from seeds
@@ -168,6 +168,45 @@ def test_grouped_config_512_problems(tg, dtype, shape):
         worst = max(worst, oracle.normwise_error(g.numpy(), ref))
     print(f"{dtype}: worst per-problem normwise error over 512 problems {worst:.3e}")
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_grouped_config_512_tuned_plan_graph_replay(tg, dtype):
+    # The 512-problem set as the benchmark runs it: plan shape tuned on the set, plan
+    # built by one eager call, the launch captured in a HIP graph and replayed.  C is
+    # restored between replays (eager copies), so every replay is checked against the
+    # same oracle result; replays must also agree bit for bit.
+    dims = inputs.grouped_dims()
+    host = _problem_set(dims, 4000)
+    alphas, betas = [1.0] * len(dims), [0.5] * len(dims)
+    As = [h[0].to(DEV) for h in host]
+    Bs = [h[1].to(DEV) for h in host]
+    C0 = [h[2].to(DEV) for h in host]
+    Cs = [c.clone() for c in C0]
+    shape = tg.gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype, reps=3)
+    print(f"{dtype}: tuned plan shape {shape}", flush=True)
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)      # plans
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
+    refs = [oracle.gemm(h[0], h[1], h[2], 1.0, 0.5) for h in host]
+    first = None
+    for r in range(3):
+        for c, c0 in zip(Cs, C0):
+            c.copy_(c0)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [c.cpu() for c in Cs]
+        worst = max(oracle.normwise_error(g.numpy(), ref) for g, ref in zip(got, refs))
+        print(f"{dtype} replay {r}: worst per-problem normwise error {worst:.3e}", flush=True)
+        assert worst <= 1e-5
+        if first is None:
+            first = got
+        else:
+            for p in range(len(dims)):
+                assert torch.equal(got[p], first[p]), f"replay {r} problem {p}"
+    del graph
 
 
 @pytest.mark.parametrize("large", [200, NEVER])

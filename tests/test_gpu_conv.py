@@ -191,7 +191,7 @@ def _run_r(tg, X, Wt, Y0, alpha, beta, dtype, path="auto", shape=0, runtime_r=Fa
 
 
 @pytest.mark.parametrize("R", [1, 5, 7, 11])
-@pytest.mark.parametrize("kernel", KERNELS[:3], ids=lambda k: f"{k[0]}{k[1]}")
+@pytest.mark.parametrize("kernel", KERNELS, ids=lambda k: f"{k[0]}{k[1]}")
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_rxr_integer_inputs_bit_exact(tg, dtype, kernel, R):
     # ragged pixel counts (more than one 128-row tile), filter taps reaching past every border
@@ -203,7 +203,7 @@ def test_rxr_integer_inputs_bit_exact(tg, dtype, kernel, R):
         np.testing.assert_array_equal(got.numpy().astype(np.float64), ref, err_msg=f"R={R} {dtype} {kernel} {shape}")
 
 
-@pytest.mark.parametrize("kernel", KERNELS[:3], ids=lambda k: f"{k[0]}{k[1]}")
+@pytest.mark.parametrize("kernel", KERNELS, ids=lambda k: f"{k[0]}{k[1]}")
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
 def test_3x3_through_the_runtime_r_kernels(tg, dtype, kernel):
     X, Wt, Y0 = _inputs_r(2, 11, 10, 16, 40, 3, seed=77, integer=True)
