@@ -26,6 +26,7 @@
 namespace tg {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -339,20 +340,43 @@ __device__ __forceinline__ uint32_t e4m3_code(float y)
     return code | sign;
 }
 
-// One workgroup per 128 x 128 tile: amax by a block reduction, then the codes.
+// One workgroup per 128 x 128 tile, one read of X: the tile is held in
+// registers (64 values per thread), its amax found by a block reduction, and
+// the codes written from the registers.  Thread t covers columns 4*(t % 32)
+// .. +3 of rows t / 32 + 8p, p = 0..15, so a wave reads two whole 512-byte
+// tile rows per load and writes them back as two runs of codes.  vec: X rows
+// allow 16-byte loads and Q rows 4-byte (e4m3) or 8-byte (bf16) stores.
 __global__ void __launch_bounds__(256) quantize_kernel(int rows, int cols, const float* X,
                                                        int64_t ldx, void* Q, int64_t ldq,
-                                                       float* S, int grid_cols, int dtype)
+                                                       float* S, int grid_cols, int dtype, int vec)
 {
     __shared__ float red[4];
     const int tile = blockIdx.x;
     const int r0 = (tile / grid_cols) * kScaleTile, c0 = (tile % grid_cols) * kScaleTile;
     const int t = threadIdx.x;
-    float m = 0.f;
-    for (int idx = t; idx < kScaleTile * kScaleTile; idx += 256) {
-        const int r = r0 + idx / kScaleTile, c = c0 + idx % kScaleTile;
-        if (r < rows && c < cols) m = fmaxf(m, fabsf(X[(int64_t)r * ldx + c]));
+    const int c = c0 + 4 * (t & 31), rt = r0 + (t >> 5);
+    const bool full = vec && r0 + kScaleTile <= rows && c0 + kScaleTile <= cols;
+    float v[16][4];
+    if (full) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            const f32x4 x = __builtin_nontemporal_load(
+                reinterpret_cast<const f32x4*>(X + (int64_t)(rt + 8 * p) * ldx + c));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[p][e] = x[e];
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 16; ++p)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[p][e] = (rt + 8 * p < rows && c + e < cols) ? X[(int64_t)(rt + 8 * p) * ldx + c + e] : 0.f;
     }
+    float m = 0.f;
+#pragma unroll
+    for (int p = 0; p < 16; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m = fmaxf(m, fabsf(v[p][e]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
     if ((t & 63) == 0) red[t >> 6] = m;
@@ -369,14 +393,37 @@ __global__ void __launch_bounds__(256) quantize_kernel(int rows, int cols, const
         }
     }
     if (t == 0) S[tile] = s;
-    for (int idx = t; idx < kScaleTile * kScaleTile; idx += 256) {
-        const int r = r0 + idx / kScaleTile, c = c0 + idx % kScaleTile;
-        if (r >= rows || c >= cols) continue;
-        const float y = X[(int64_t)r * ldx + c] / s;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const int r = rt + 8 * p;
+        if (!full && r >= rows) continue;
         if (dtype == TGEMM_FP8_E4M3) {
-            static_cast<uint8_t*>(Q)[(int64_t)r * ldq + c] = (uint8_t)e4m3_code(y);
+            uint32_t q[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q[e] = e4m3_code(v[p][e] / s);
+            uint8_t* dst = static_cast<uint8_t*>(Q) + (int64_t)r * ldq + c;
+            if (full) {
+                *reinterpret_cast<uint32_t*>(dst) = q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (c + e < cols) dst[e] = (uint8_t)q[e];
+            }
         } else {
-            static_cast<__bf16*>(Q)[(int64_t)r * ldq + c] = (__bf16)y;
+            __bf16 q[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q[e] = (__bf16)(v[p][e] / s);
+            __bf16* dst = static_cast<__bf16*>(Q) + (int64_t)r * ldq + c;
+            if (full) {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] = __builtin_bit_cast(uint16_t, q[e]);
+                *reinterpret_cast<uint2*>(dst) = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (c + e < cols) dst[e] = q[e];
+            }
         }
     }
 }
@@ -385,8 +432,11 @@ hipError_t launch_quantize(int rows, int cols, const float* X, int64_t ldx, void
                            float* S, int dtype, hipStream_t s)
 {
     const int gr = (rows + kScaleTile - 1) / kScaleTile, gc = (cols + kScaleTile - 1) / kScaleTile;
+    const int64_t qes = dtype == TGEMM_FP8_E4M3 ? 1 : 2;
+    const int vec = reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 4 == 0 &&
+                    reinterpret_cast<uintptr_t>(Q) % (4 * qes) == 0 && ldq % 4 == 0;
     hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)(gr * gc)), dim3(256), 0, s, rows, cols, X,
-                       ldx, Q, ldq, S, gc, dtype);
+                       ldx, Q, ldq, S, gc, dtype, vec);
     return hipGetLastError();
 }
 

@@ -603,13 +603,17 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     // pipeline cover them; loading them where they are used would drain the
     // panels in flight at every block boundary.  (They are vector loads: C is
     // written by the same kernel and may alias the scales.)
+    // A wave tile no larger than a 128 x 128 scale tile lies inside one (tiles
+    // start at multiples of their size), so one product serves all its blocks.
+    constexpr bool one_scale = CF::WTM <= 128 && CF::WTN <= 128;
+    constexpr int SM = one_scale ? 1 : CF::TM, SN = one_scale ? 1 : CF::TN;
     int kb_cur = 0;
-    float sc_cur[CF::TM][CF::TN], sc_next[CF::TM][CF::TN];
-    auto load_scales = [&](int kb, float (&dst)[CF::TM][CF::TN]) {
+    float sc_cur[SM][SN], sc_next[SM][SN];
+    auto load_scales = [&](int kb, float (&dst)[SM][SN]) {
 #pragma unroll
-        for (int i = 0; i < CF::TM; ++i)
+        for (int i = 0; i < SM; ++i)
 #pragma unroll
-            for (int j = 0; j < CF::TN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
+            for (int j = 0; j < SN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
     };
     if (scaled) load_scales(0, sc_cur);
     auto prefetch = [&](int s) {  // during panel s: the scales of panel s + 1 if it opens a block
@@ -626,11 +630,14 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j) {
-                const float ratio = sc_cur[i][j] / sc_next[i][j];
+                const float ratio = sc_cur[i % SM][j % SN] / sc_next[i % SM][j % SN];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
-                sc_cur[i][j] = sc_next[i][j];
             }
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+            for (int j = 0; j < SN; ++j) sc_cur[i][j] = sc_next[i][j];
         kb_cur = kb;
     };
     if constexpr (NS == 2 && (CF::MODE == MODE_FP8 || (CF::NG == 1 && CF::BM >= 128))) {
@@ -736,7 +743,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j) {
             const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
-            const float sc = a.alpha * (scaled ? sc_cur[i][j] : 1.f);
+            const float sc = a.alpha * (scaled ? sc_cur[i % SM][j % SN] : 1.f);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);

@@ -97,6 +97,26 @@ def test_quantiser_bit_exact(tg, dtype, shape):
     np.testing.assert_array_equal(Qg, Qr)
 
 
+@pytest.mark.parametrize("dtype", ["fp8", "bf16"])
+@pytest.mark.parametrize("pad", [0, 3], ids=["aligned", "ld+3"])
+def test_quantiser_full_tiles_both_load_widths(tg, dtype, pad):
+    # whole 128 x 128 tiles: aligned rows take the 16-byte loads, a row stride of
+    # cols + 3 the per-element ones; a ragged last row and column of tiles too
+    rows, cols = 300, 388
+    A, _ = inputs.lowprec_inputs(rows, 4, cols, seed=33)
+    Xw = torch.full((rows, cols + pad), float("nan"))
+    Xw[:, :cols] = A
+    Xd = Xw.to(DEV)[:, :cols]
+    Qr, Sr = _oracle_quant(A.numpy(), dtype)
+    Q, S = tg.quantize_tiles(Xd, dtype)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(S.cpu().numpy(), Sr)
+    Qg = Q.cpu().numpy()
+    if dtype == "bf16":
+        Qg = Qg.view(np.uint16)
+    np.testing.assert_array_equal(Qg, Qr)
+
+
 def test_quantiser_special_values(tg):
     # ties, saturation, subnormal codes and signed zero inside one tile
     vals = np.array([448.0, -448.0, 1.0625, 1.1875, 0.0009765625, 0.0029296875, -0.0, 0.0,
