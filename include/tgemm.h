@@ -380,11 +380,18 @@ const char* tgemm_status_string(int status);
 int tgemm_set_policy(const char* policy);
 
 /* Number of compiled schedules and the parameters of one of them.
- * info receives 8 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes.
+ * info receives 9 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes,
+ * split.
  * vec = 4: 16-byte global loads (16-byte aligned bases, row strides multiple of
  * 16 bytes); vec = 1: 4-byte loads (any alignment); vec = 0: packed operands
  * (a pre-pass copies A and B^T, converted and zero-padded, into a workspace
  * the library owns per device and stream; any alignment).
+ * split = 1: stream-K (packed schedules only): one resident wave of
+ * workgroups splits the (tile, K panel) iterations evenly; a tile shared by
+ * several workgroups is summed, in K order, by the last of them to finish,
+ * from partial sums in the stream's workspace (2 * slots * BM * BN floats more)
+ * and per-tile counters (4 MiB per device and stream, allocated on first use).
+ * split = 0: one workgroup per tile.
  * Host-only: no HIP call. */
 int tgemm_schedule_count(void);
 int tgemm_schedule_info(int schedule_id, int* info);
@@ -457,7 +464,7 @@ int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m,
                     int64_t step, float lr, void* stream);
 
 /*
- * Learned cost model (project addition).  A 20-feature ReLU MLP (3 hidden
+ * Learned cost model (project addition).  A 21-feature ReLU MLP (3 hidden
  * layers of 256) predicts the log runtime of (problem, schedule, tile order).
  *
  * tgemm_costmodel_train: reads the valid records of a tuning database written
@@ -481,7 +488,7 @@ int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m,
  * tgemm_costmodel_select: the prediction when the model can answer, else
  *   exhaustive autotuning (tgemm_autotune with `reps`, appending to db_path);
  *   *used_fallback says which.
- * tgemm_costmodel_features: the feature vector (20 floats, host) of one
+ * tgemm_costmodel_features: the feature vector (21 floats, host) of one
  *   candidate.  Host-only.
  */
 int tgemm_costmodel_train(const char* db_path, const char* weights_out, int epochs, int batch,

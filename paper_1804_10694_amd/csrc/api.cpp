@@ -288,6 +288,7 @@ int tgemm_schedule_info(int id, int* info)
     info[5] = d.WGN;
     info[6] = d.vec;
     info[7] = d.lds_bytes;
+    info[8] = d.split;
     return TGEMM_SUCCESS;
 }
 

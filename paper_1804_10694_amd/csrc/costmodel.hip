@@ -37,12 +37,12 @@ bool vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int dtype);
 
 namespace {
 
-constexpr int kFeatures = 20;
+constexpr int kFeatures = 21;
 constexpr int kHidden = 256;
 constexpr int kLayers = 4;  // 3 hidden layers of 256, one output
 const int kDims[kLayers + 1] = {kFeatures, kHidden, kHidden, kHidden, 1};
 constexpr uint32_t kMagic = 0x4d434754u;  // "TGCM"
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 // Tile-order variants the model ranks (the autotuner's set).
 const int kVariants[][2] = {{1, 0}, {4, 1}, {8, 1}, {16, 1}};
 // A shape is out of distribution when a log2 dimension lies this far outside
@@ -86,6 +86,7 @@ void cost_features(int64_t M, int64_t N, int64_t K, int dtype, const SchedDesc& 
     f[i++] = (float)lg2(flops / bytes);
     f[i++] = (float)lg2(kpanels);
     f[i++] = (float)d.lds_bytes / (160.f * 1024.f);
+    f[i++] = (float)d.split;                                        // stream-K
 }
 
 namespace {

@@ -66,63 +66,274 @@ __global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) packed_kernel(Packed
     packed_tile<CF>(a, tc.tm * CF::BM, tc.tn * CF::BN, lds);
 }
 
+// Stream-K: the iterations (tile t, K panel p), numbered t * panels + p with
+// tiles in the grouped order of map_tile, are split into `grid` contiguous,
+// nearly equal ranges, one per workgroup of a single resident wave, so no
+// workgroup idles in a last partial wave of tiles.  A tile covered by several
+// ranges is summed by whichever of its workgroups finishes last: each writes
+// its partial sums to its own slot of `ws` and counts itself in cnt[t]; the
+// last one adds the partials in K order (so the result does not depend on
+// which workgroup that is) and writes C.  Nothing waits on another workgroup.
+// The partials are written and read with device-scope (agent) atomic stores
+// and loads, which are coherent across the XCDs' L2 caches on their own; a
+// device-scope fence would instead write back and invalidate the whole L2 of
+// the XCD, and with it the panels the other tiles there are reading.
+struct SkArgs {
+    float* ws;   // 2 * grid slots of BM * BN floats: a range's first and last tile
+    int* cnt;    // per-tile arrival counts; zero before and after every launch
+    int total;   // tiles * panels (< 2^31)
+    int grid;    // workgroups; every one has at least one iteration (grid <= total)
+    int panels;  // K panels per tile
+    int q, r;    // total = q * grid + r: ranges 0 .. r-1 hold q + 1 iterations, the others q
+};
+
+__device__ __forceinline__ int sk_begin(const SkArgs& k, int v) { return v * k.q + min(v, k.r); }
+// The workgroup whose range holds iteration i.
+__device__ __forceinline__ int sk_owner(const SkArgs& k, int i)
+{
+    const int big = k.r * (k.q + 1);
+    return i < big ? i / (k.q + 1) : k.r + (i - big) / k.q;
+}
+
+// Epilogue of a stream-K range that covers part of tile t.
+template <class CF>
+struct SkPartial {
+    const PackedArgs& a;
+    const SkArgs& k;
+    int t, v, m0, n0;
+    int* flag;  // LDS word: this workgroup sums the tile
+
+    __device__ __forceinline__ float* slot(int u) const
+    {
+        const bool first = t == sk_begin(k, u) / k.panels;
+        return k.ws + (int64_t)(2 * u + (first ? 0 : 1)) * (CF::BM * CF::BN);
+    }
+
+    // Sum r of block (i, j) of this lane in a slot: the 64 lanes of a wave hold
+    // 64 consecutive floats, so each (device-scope, 4-byte) store or load of a
+    // wave covers 256 contiguous bytes.
+    __device__ __forceinline__ static int elem(int wave, int i, int j, int r, int lane)
+    {
+        return (((wave * CF::TM + i) * CF::TN + j) * 16 + r) * 64 + lane;
+    }
+
+    template <class SC>
+    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+                                               int wn0, int lane) const
+    {
+        asm volatile("" : "+v"(lane));  // keep the slot addresses out of the main loop
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        float* mine = slot(v);
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const float f = sc(i, j);
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    __hip_atomic_store(mine + elem(wave, i, j, r, lane), f * acc[i][j][r], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        const int u0 = sk_owner(k, t * k.panels), u1 = sk_owner(k, (t + 1) * k.panels - 1);
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed ...
+        __syncthreads();                // ... and every thread's: the partial is complete
+        if (threadIdx.x == 0) {
+            const int last = atomicAdd(&k.cnt[t], 1) == u1 - u0;
+            // every range has arrived: the counter is ready for the next launch
+            if (last) __hip_atomic_store(&k.cnt[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *flag = last;
+        }
+        __syncthreads();
+        if (!*flag) return;
+        // sum every range's partial (this one's included, read back) in K order,
+        // four sums at a time
+        const int h = lane >> 5, l32 = lane & 31;
+        const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
+        const bool read_c = (a.beta != 0.f);
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    f32x4 s4 = {0.f, 0.f, 0.f, 0.f};
+                    for (int u = u0; u <= u1; ++u) {
+                        const float* src = slot(u);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            s4[e] += __hip_atomic_load(src + elem(wave, i, j, 4 * q + e, lane), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = 4 * q + e;
+                        const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
+                        const int col = c0 + l32;
+                        if (!full && (row >= a.M || col >= a.N)) continue;
+                        float* pc = a.C + (int64_t)row * a.ldc + col;
+                        float val = a.alpha * s4[e];
+                        if (read_c) val = fmaf(a.beta, *pc, val);
+                        *pc = val;
+                    }
+                }
+            }
+    }
+};
+
+template <class CF>
+struct SkStore {
+    TileStore<CF> whole;
+    SkPartial<CF> part;
+    bool is_whole;
+    template <class SC>
+    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+                                               int wn0, int lane) const
+    {
+        if (is_whole) whole(acc, sc, wm0, wn0, lane);
+        else part(acc, sc, wm0, wn0, lane);
+    }
+};
+
+template <class CF>
+__global__ void __launch_bounds__(CF::NT, CF::WAVES_PER_EU) packed_sk_kernel(PackedArgs a, SkArgs k)
+{
+    __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
+    __shared__ int flag;
+    // the workgroups of one XCD (ids equal mod 8) take consecutive ranges, so
+    // the tiles they share panels with meet in that XCD's L2
+    const int per_xcd = k.grid / kNumXcd;
+    const int v = (k.grid % kNumXcd == 0) ? ((int)blockIdx.x % kNumXcd) * per_xcd + (int)blockIdx.x / kNumXcd
+                                          : (int)blockIdx.x;
+    const int end = sk_begin(k, v + 1);
+    using AL = PackedRowsA<CF>;
+    for (int it = sk_begin(k, v); it < end;) {
+        const int t = it / k.panels;
+        const int pb = it - t * k.panels;
+        const int pe = min(k.panels, pb + (end - it));
+        const TileCoord tc = map_tile(t, a.tiles_m, a.tiles_n, a.group_m, 0);
+        const int m0 = tc.tm * CF::BM, n0 = tc.tn * CF::BN;
+        const SkStore<CF> epi{TileStore<CF>{a, m0, n0}, SkPartial<CF>{a, k, t, v, m0, n0, &flag},
+                              pb == 0 && pe == k.panels};
+        if ((CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA)
+            packed_tile_range<CF, AL, PackedRowsB<CF>, PackedOps<CF>, true>(a, m0, n0, lds, typename AL::Geom(),
+                                                                            pb, pe - pb, epi);
+        else
+            packed_tile_range<CF, AL, PackedRowsB<CF>, PackedOps<CF>, false>(a, m0, n0, lds, typename AL::Geom(),
+                                                                             pb, pe - pb, epi);
+        it += pe - pb;
+        __syncthreads();  // every wave is done with the LDS stages (and the flag) before the next tile
+    }
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
 struct PSched {
     int dtype, mode, BM, BN, BK, WGM, WGN, lds, threads;
     void (*kernel)(PackedArgs);
+    void (*sk_kernel)(PackedArgs, SkArgs);  // stream-K form, or null
 };
 
 #define TG_PSCHED(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                             \
     {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::LDS_BYTES,              \
-     PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
+     PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>, \
+     nullptr}
+// A schedule that also has a stream-K form (a second registry entry).
+#define TG_PSCHED_SK(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                          \
+    {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::LDS_BYTES,              \
+     PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>, \
+     &packed_sk_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
 
-const PSched kPacked[] = {
+constexpr PSched kPacked[] = {
     // two workgroups per CU (LDS <= 80 KB), 4 waves each
     TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 32, 2, 2, 2),
     TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 4),
     // four workgroups per CU (LDS 32 KB): one wave of 128 x 128 tiles covers
     // 1024 tiles, for problems whose tile count falls just past 512
-    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 2),
-    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 16, 2, 2, 2),
+    TG_PSCHED_SK(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 2),
+    TG_PSCHED_SK(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 16, 2, 2, 2),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 32, 2, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 64, 2, 2, 2),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 16, 2, 2, 3),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 128, 32, 2, 2, 3),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 128, 64, 2, 2, 3),
     // two workgroups per CU of 8 waves, each wave 32 x 128 of the tile
-    TG_PSCHED(TGEMM_F32, MODE_F32, 128, 256, 16, 4, 2, 3),
+    TG_PSCHED_SK(TGEMM_F32, MODE_F32, 128, 256, 16, 4, 2, 3),
     // one workgroup per CU, 8 waves
     TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 32, 2, 4, 2),
     TG_PSCHED(TGEMM_F32, MODE_F32, 256, 256, 16, 2, 4, 4),
     TG_PSCHED(TGEMM_F32, MODE_F32, 256, 128, 32, 2, 4, 3),
-    TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4, 2),
+    TG_PSCHED_SK(TGEMM_F32_BF16X3, MODE_X3, 256, 256, 32, 2, 4, 2),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 4, 3),
     TG_PSCHED(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2, 2),
-    TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 64, 2, 4, 2),
+    TG_PSCHED_SK(TGEMM_BF16, MODE_BF16, 256, 256, 64, 2, 4, 2),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 256, 256, 32, 2, 4, 4),
     TG_PSCHED(TGEMM_BF16, MODE_BF16, 128, 128, 64, 2, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 2, 4, 2),
-    TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 4, 2, 2),
+    TG_PSCHED_SK(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 4, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 64, 2, 4, 4),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2, 2),
 };
 constexpr int kNumPacked = sizeof(kPacked) / sizeof(kPacked[0]);
+constexpr int count_sk()
+{
+    int n = 0;
+    for (const PSched& p : kPacked) n += p.sk_kernel != nullptr;
+    return n;
+}
+constexpr int kNumSk = count_sk();
 
 // Registry entries (kernel pointer unused: packed schedules launch through
-// run_packed); vec = 0 marks "packed, any alignment".
-SchedDesc g_packed_desc[kNumPacked];
+// run_packed); vec = 0 marks "packed, any alignment".  Entries kNumPacked ..
+// are the stream-K forms, in table order; g_sk_of maps them to their row.
+SchedDesc g_packed_desc[kNumPacked + kNumSk];
+int g_sk_of[kNumSk > 0 ? kNumSk : 1];
 struct DescInit {
     DescInit()
     {
+        int n = 0;
         for (int i = 0; i < kNumPacked; ++i) {
             const PSched& p = kPacked[i];
             g_packed_desc[i] = SchedDesc{p.dtype, p.BM, p.BN, p.BK, p.WGM, p.WGN, 0, p.lds, p.threads,
                                          nullptr};
+            if (p.sk_kernel) {
+                g_packed_desc[kNumPacked + n] = g_packed_desc[i];
+                g_packed_desc[kNumPacked + n].split = 1;
+                g_sk_of[n++] = i;
+            }
         }
     }
 } g_desc_init;
+
+// Stream-K arrival counters, one array per (device, stream), zeroed when it is
+// allocated and left zeroed by every launch.  Sized for kSkMaxTiles tiles.
+constexpr int kSkMaxTiles = 1 << 20;
+std::map<std::pair<int, hipStream_t>, int*> g_skcnt;
+
+__global__ void zero_ints(int* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Workgroups of one resident wave of a kernel (CUs x occupancy), per device.
+int resident_slots(const void* fn, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(std::make_pair(dev, fn));
+    if (it != cache.end()) return it->second;
+    int cus = 256, per_cu = 1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    cache[std::make_pair(dev, fn)] = cus * per_cu;
+    return cus * per_cu;
+}
 
 // Per (device, stream) packing workspace, grown on demand.  A buffer that is
 // outgrown is retired, not freed: a HIP graph captured over an earlier call
@@ -149,8 +360,39 @@ void free_workspace(Workspace& w)
 
 const SchedDesc* packed_schedules(int* n)
 {
-    *n = kNumPacked;
+    *n = kNumPacked + kNumSk;
     return g_packed_desc;
+}
+
+// Bytes of stream-K partial sums for packed schedule `pid` (0 unless it is a
+// stream-K form), and the per-stream counter array it needs.
+size_t sk_workspace_bytes(int pid)
+{
+    if (pid < kNumPacked) return 0;
+    const PSched& p = kPacked[g_sk_of[pid - kNumPacked]];
+    const int slots = resident_slots(reinterpret_cast<const void*>(p.sk_kernel), p.threads);
+    return (size_t)2 * slots * p.BM * p.BN * sizeof(float);
+}
+
+int sk_counters(hipStream_t s, int** out)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int*& c = g_skcnt[std::make_pair(dev, s)];
+    if (!c) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+            return TGEMM_CAPTURE_UNPLANNED;
+        if (hipMalloc(&c, (size_t)kSkMaxTiles * sizeof(int)) != hipSuccess) {
+            c = nullptr;
+            return TGEMM_ALLOC_FAILED;
+        }
+        hipLaunchKernelGGL(zero_ints, dim3(1024), dim3(256), 0, s, c, kSkMaxTiles);
+        if (hipGetLastError() != hipSuccess) return TGEMM_LAUNCH_FAILED;
+    }
+    *out = c;
+    return TGEMM_SUCCESS;
 }
 
 // Bytes of packing workspace for a problem.
@@ -191,9 +433,15 @@ void packed_release(hipStream_t s)
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_pair(dev, s));
-    if (it == g_ws.end()) return;
-    free_workspace(it->second);
-    g_ws.erase(it);
+    if (it != g_ws.end()) {
+        free_workspace(it->second);
+        g_ws.erase(it);
+    }
+    auto ic = g_skcnt.find(std::make_pair(dev, s));
+    if (ic != g_skcnt.end()) {
+        if (ic->second) (void)hipFree(ic->second);
+        g_skcnt.erase(ic);
+    }
 }
 
 void packed_shutdown()
@@ -201,6 +449,9 @@ void packed_shutdown()
     std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto& kv : g_ws) free_workspace(kv.second);
     g_ws.clear();
+    for (auto& kv : g_skcnt)
+        if (kv.second) (void)hipFree(kv.second);
+    g_skcnt.clear();
 }
 
 namespace {
@@ -263,11 +514,15 @@ bool packed_k_ok(int64_t K, int dtype)
     return kPackRows * packed_kp(K, es) * es <= INT32_MAX;
 }
 
+// pid < kNumPacked: one workgroup per tile.  pid >= kNumPacked: the stream-K
+// form of row g_sk_of[pid - kNumPacked], with its partial sums after the packed
+// operands in `ws` and the stream's counters `cnt`.
 int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
                   const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
-                  int64_t ldc, int group_m, int xcd_remap, void* ws, hipStream_t s)
+                  int64_t ldc, int group_m, int xcd_remap, void* ws, int* cnt, hipStream_t s)
 {
-    const PSched& p = kPacked[pid];
+    const bool sk = pid >= kNumPacked;
+    const PSched& p = kPacked[sk ? g_sk_of[pid - kNumPacked] : pid];
     if (!packed_k_ok(K, p.dtype)) return TGEMM_NOT_SUPPORTED;
     const int64_t Mp = (M + kPackRows - 1) / kPackRows * kPackRows;
     const int64_t Np = (N + kPackRows - 1) / kPackRows * kPackRows;
@@ -304,7 +559,27 @@ int run_packed_ws(int pid, int64_t M, int64_t N, int64_t K, float alpha, const v
     a.group_m = group_m < 1 ? 1 : group_m;
     a.xcd_remap = xcd_remap ? 1 : 0;
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
-    hipLaunchKernelGGL(p.kernel, dim3((unsigned)(a.tiles_m * a.tiles_n)), dim3(p.threads), 0, s, a);
+    const int tiles = a.tiles_m * a.tiles_n;
+    if (sk) {
+        SkArgs k;
+        k.panels = (int)((K + p.BK - 1) / p.BK);
+        const int64_t total = (int64_t)tiles * k.panels;
+        if (tiles > kSkMaxTiles || total > INT32_MAX || !cnt) return TGEMM_NOT_SUPPORTED;
+        k.total = (int)total;
+        const int slots = resident_slots(reinterpret_cast<const void*>(p.sk_kernel), p.threads);
+        // whole XCD groups, and at least one iteration per workgroup
+        int grid = std::min(slots, k.total);
+        if (grid >= kNumXcd) grid -= grid % kNumXcd;
+        k.grid = grid;
+        k.q = k.total / grid;
+        k.r = k.total % grid;
+        k.cnt = cnt;
+        k.ws = reinterpret_cast<float*>(base + packed_workspace_bytes(M, N, K, p.dtype));
+        a.group_m = group_m < 1 ? 1 : group_m;
+        hipLaunchKernelGGL(p.sk_kernel, dim3((unsigned)grid), dim3(p.threads), 0, s, a, k);
+    } else {
+        hipLaunchKernelGGL(p.kernel, dim3((unsigned)tiles), dim3(p.threads), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
 }
 
@@ -340,12 +615,15 @@ int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void
                const float* sA, const void* B, int64_t ldb, const float* sB, float beta, float* C,
                int64_t ldc, int group_m, int xcd_remap, hipStream_t s)
 {
-    if (!packed_k_ok(K, kPacked[pid].dtype)) return TGEMM_NOT_SUPPORTED;
+    const int dtype = g_packed_desc[pid].dtype;
+    if (!packed_k_ok(K, dtype)) return TGEMM_NOT_SUPPORTED;
     void* ws = nullptr;
-    const int rc = packed_workspace(s, packed_workspace_bytes(M, N, K, kPacked[pid].dtype), &ws);
+    int* cnt = nullptr;
+    int rc = packed_workspace(s, packed_workspace_bytes(M, N, K, dtype) + sk_workspace_bytes(pid), &ws);
+    if (rc == TGEMM_SUCCESS && pid >= kNumPacked) rc = sk_counters(s, &cnt);
     if (rc != TGEMM_SUCCESS) return rc;
     return run_packed_ws(pid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, group_m,
-                         xcd_remap, ws, s);
+                         xcd_remap, ws, cnt, s);
 }
 
 }  // namespace tg
@@ -382,6 +660,9 @@ extern "C" int tgemm_noalloc(int64_t M, int64_t N, int64_t K, float alpha, const
         return TGEMM_SCRATCH_TOO_SMALL;
     void* ws = nullptr;
     if ((rc = scratch_address(&ws)) != TGEMM_SUCCESS) return rc;
-    return run_packed_ws(pid, M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, ch.group_m,
-                         ch.xcd_remap, ws, s);
+    // a stream-K form needs counters the library allocates: its row runs instead,
+    // one workgroup per tile (same tiles and panels, another summation order)
+    const int row = pid >= kNumPacked ? g_sk_of[pid - kNumPacked] : pid;
+    return run_packed_ws(row, M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, ch.group_m,
+                         ch.xcd_remap, ws, nullptr, s);
 }

@@ -15,6 +15,8 @@ struct SchedDesc {
     int lds_bytes;  // LDS footprint (both stages)
     int threads;
     void (*kernel)(GemmArgs);
+    int split = 0;  // 1: stream-K (packed schedules): the (tile, K panel) iterations are split
+                    // evenly over one wave of resident workgroups
 };
 
 // All compiled schedules, ids 0..num_schedules()-1 (tables of every kernel

@@ -557,16 +557,58 @@ struct PackedRowsB {
     }
 };
 
-// One BM x BN macro-tile at (m0, n0) of problem `a`; `lds` holds
-// CF::LDS_BYTES.  AL and BL bring the A and B panels into an LDS stage (A
-// first, B at offset NARR * LDS_A), each issuing a fixed number of loads per
-// wave per panel (AL::LOADS + BL::LOADS in all); OP reads the MFMA operands
-// from a stage and runs the MFMAs.  By default both operands come from packed
-// rows (of A and of B^T), which must extend to m0 + BM and n0 + BN, and K to
-// a multiple of BK, with zeros beyond K.
-template <class CF, class AL = PackedRowsA<CF>, class BL = PackedRowsB<CF>, class OP = PackedOps<CF>>
-__device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds,
-                                            const typename AL::Geom& geom = typename AL::Geom())
+// Epilogue of a whole tile: C = alpha * scale * acc (+ beta * C), predicated
+// only on partial tiles.  sc(i, j) is the scale product that multiplies the
+// sums of block (i, j) (1 for unscaled forms).
+template <class CF>
+struct TileStore {
+    const PackedArgs& a;
+    int m0, n0;
+    template <class SC>
+    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+                                               int wn0, int lane) const
+    {
+        // the addresses below are computed here, not hoisted out of a loop over
+        // tiles where they would hold registers through the main loop
+        asm volatile("" : "+v"(lane));
+        const int h = lane >> 5, l32 = lane & 31;
+        const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
+        const bool read_c = (a.beta != 0.f);
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::TN; ++j) {
+                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+                const float f = a.alpha * sc(i, j);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const int col = c0 + l32;
+                    if (!full && (row >= a.M || col >= a.N)) continue;
+                    float* p = a.C + (int64_t)row * a.ldc + col;
+                    float v = f * acc[i][j][r];
+                    if (read_c) v = fmaf(a.beta, *p, v);
+                    *p = v;
+                }
+            }
+    }
+};
+
+// Panels [p0, p0 + np) of one BM x BN macro-tile at (m0, n0) of problem `a`;
+// `lds` holds CF::LDS_BYTES.  AL and BL bring the A and B panels into an LDS
+// stage (A first, B at offset NARR * LDS_A), each issuing a fixed number of
+// loads per wave per panel (AL::LOADS + BL::LOADS in all); OP reads the MFMA
+// operands from a stage and runs the MFMAs; EPI receives the sums (see
+// TileStore).  By default both operands come from packed rows (of A and of
+// B^T), which must extend to m0 + BM and n0 + BN, and K to a multiple of BK,
+// with zeros beyond K.  The caller separates consecutive calls that reuse
+// `lds` with a barrier.
+// SCALED: a.sA and a.sB hold per-tile scales (bf16 and e4m3 only; the caller
+// branches on a.sA once, so each loop is compiled for one case).
+template <class CF, class AL, class BL, class OP, bool SCALED, class EPI>
+__device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, int n0, char* lds,
+                                                  const typename AL::Geom& geom, int p0, int np,
+                                                  const EPI& epi)
 {
     const int t = threadIdx.x, lane = t & 63;
     // the wave index is uniform; readfirstlane lets the compiler keep it (and the
@@ -577,7 +619,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     al.init(a, m0, lane, wave, geom);
     BL bl;
     bl.init(a, n0, lane, wave);
-    const bool scaled = (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA;
+    constexpr bool scaled = SCALED && (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8);
 
     f32x16 acc[CF::TM][CF::TN];
 #pragma unroll
@@ -587,10 +629,10 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    const int npanel = (a.K + CF::BK - 1) / CF::BK;
-    auto issue = [&](int panel, char* stage) {
-        al.issue(panel, stage);
-        bl.issue(panel, stage + CF::NARR * CF::LDS_A);
+    const int npanel = np;
+    auto issue = [&](int panel, char* stage) {  // panel: index within the range
+        al.issue(p0 + panel, stage);
+        bl.issue(p0 + panel, stage + CF::NARR * CF::LDS_A);
     };
 
     // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
@@ -607,7 +649,7 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
     // start at multiples of their size), so one product serves all its blocks.
     constexpr bool one_scale = CF::WTM <= 128 && CF::WTN <= 128;
     constexpr int SM = one_scale ? 1 : CF::TM, SN = one_scale ? 1 : CF::TN;
-    int kb_cur = 0;
+    int kb_cur = (p0 * CF::BK) / 128;
     float sc_cur[SM][SN], sc_next[SM][SN];
     auto load_scales = [&](int kb, float (&dst)[SM][SN]) {
 #pragma unroll
@@ -615,25 +657,38 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
 #pragma unroll
             for (int j = 0; j < SN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
     };
-    if (scaled) load_scales(0, sc_cur);
+    if (scaled) load_scales(kb_cur, sc_cur);
     auto prefetch = [&](int s) {  // during panel s: the scales of panel s + 1 if it opens a block
         if (!scaled || s + 1 >= npanel) return;
-        const int kb = ((s + 1) * CF::BK) / 128;
-        if (kb != (s * CF::BK) / 128) load_scales(kb, sc_next);
+        const int kb = ((p0 + s + 1) * CF::BK) / 128;
+        if (kb != ((p0 + s) * CF::BK) / 128) load_scales(kb, sc_next);
     };
     // new K scale block at panel s: move acc to the new block's scale product
     auto rescale = [&](int s) {
         if (!scaled) return;
-        const int kb = (s * CF::BK) / 128;
+        const int kb = ((p0 + s) * CF::BK) / 128;
         if (s == 0 || kb == kb_cur) return;
+        if constexpr (one_scale) {
+            // one product per wave: nothing to do when it does not change (acc * 1 == acc)
+            const float ratio = sc_cur[0][0] / sc_next[0][0];
+            if (ratio != 1.f) {
 #pragma unroll
-        for (int i = 0; i < CF::TM; ++i)
+                for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
-            for (int j = 0; j < CF::TN; ++j) {
-                const float ratio = sc_cur[i % SM][j % SN] / sc_next[i % SM][j % SN];
+                    for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                for (int j = 0; j < CF::TN; ++j) {
+                    const float ratio = sc_cur[i][j] / sc_next[i][j];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                }
+        }
 #pragma unroll
         for (int i = 0; i < SM; ++i)
 #pragma unroll
@@ -735,26 +790,19 @@ __device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0,
         }
     }
 
-    const int h = lane >> 5, l32 = lane & 31;
-    const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
-    const bool read_c = (a.beta != 0.f);
-#pragma unroll
-    for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < CF::TN; ++j) {
-            const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
-            const float sc = a.alpha * (scaled ? sc_cur[i % SM][j % SN] : 1.f);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = c0 + l32;
-                if (!full && (row >= a.M || col >= a.N)) continue;
-                float* p = a.C + (int64_t)row * a.ldc + col;
-                float v = sc * acc[i][j][r];
-                if (read_c) v = fmaf(a.beta, *p, v);
-                *p = v;
-            }
-        }
+    epi(acc, [&](int i, int j) { return scaled ? sc_cur[i % SM][j % SN] : 1.f; }, wm0, wn0, lane);
+}
+
+// One whole macro-tile (all K panels) with the standard epilogue.
+template <class CF, class AL = PackedRowsA<CF>, class BL = PackedRowsB<CF>, class OP = PackedOps<CF>>
+__device__ __forceinline__ void packed_tile(const PackedArgs& a, int m0, int n0, char* lds,
+                                            const typename AL::Geom& geom = typename AL::Geom())
+{
+    const int np = (a.K + CF::BK - 1) / CF::BK;
+    if ((CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8) && a.sA)
+        packed_tile_range<CF, AL, BL, OP, true>(a, m0, n0, lds, geom, 0, np, TileStore<CF>{a, m0, n0});
+    else
+        packed_tile_range<CF, AL, BL, OP, false>(a, m0, n0, lds, geom, 0, np, TileStore<CF>{a, m0, n0});
 }
 
 }  // namespace tg
