@@ -144,8 +144,9 @@ int tgemm_scaled(int64_t M, int64_t N, int64_t K, float alpha,
  * Per-tile quantiser (project addition; not in the paper).  X is a rows x
  * cols float32 row-major device matrix with row stride ldx.  For each
  * 128 x 128 tile (the last ones partial): amax = max |x|;
- *   TGEMM_FP8_E4M3: s = fl32(amax / 448) (s = 1 if amax == 0),
- *                   q = round-to-nearest-even, saturating E4M3FN of fl32(x/s);
+ *   TGEMM_FP8_E4M3: s = the power of two with amax / s in (224, 448]
+ *                   (exponent clamped to [-126, 127]; s = 1 if amax == 0),
+ *                   q = round-to-nearest-even, saturating E4M3FN of x/s;
  *   TGEMM_BF16:     s = 2^ceil(log2(amax)) (s = 1 if amax == 0),
  *                   q = round-to-nearest-even bf16 of x/s.
  * Q (device, element size 1 or 2 bytes, row stride ldq) and S (device,

@@ -17,8 +17,10 @@ implements:
                        infinities), nearest-even, values beyond 448 saturate.
   quantize_tiles_*     one FP32 scale per 128 x 128 tile of a row-major matrix
                        (the last tiles may be partial):
-                         e4m3: s = fl32(amax / 448), s = 1 when amax = 0,
-                               q = e4m3_rne_sat(fl32(x / s));
+                         e4m3: s = the power of two with amax / s in
+                               (224, 448] (exponent clamped to the float32
+                               normal range), s = 1 when amax = 0,
+                               q = e4m3_rne_sat(x / s) (exact division);
                          bf16: s = 2^ceil(log2 amax), s = 1 when amax = 0,
                                q = RNE_bf16(x / s) (exact power-of-two scale).
   dequantize_tiles     q * s in FP64 (exact: at most 8 + 24 significant bits).
@@ -161,9 +163,15 @@ def quantize_tiles_e4m3(X, tile=TILE):
     for bi, bj, rs, cs in _tiles(rows, cols, tile):
         blk = X[rs, cs]
         amax = np.float32(np.max(np.abs(blk))) if blk.size else np.float32(0)
-        s = np.float32(amax / np.float32(E4M3_MAX)) if amax > 0 else np.float32(1.0)
+        s = np.float32(1.0)
+        if amax > 0:
+            # amax = f 2^p with 0.5 <= f < 1, and 448 = 0.875 * 2^9: the smallest e
+            # with 448 * 2^e >= amax is p - 9 when f <= 0.875, else p - 8
+            f, p = np.frexp(amax)
+            e = int(p) - 9 if f <= 0.875 else int(p) - 8
+            s = np.float32(np.ldexp(1.0, min(max(e, -126), 127)))
         S[bi, bj] = s
-        y = (blk / s).astype(np.float32)          # float32 quotient, IEEE rounded
+        y = (blk / s).astype(np.float32)          # exact: s is a power of two
         Q[rs, cs] = e4m3_encode(e4m3_rne_sat(y))
     return Q, S
 

@@ -382,14 +382,18 @@ __global__ void __launch_bounds__(256) quantize_kernel(int rows, int cols, const
     if ((t & 63) == 0) red[t >> 6] = m;
     __syncthreads();
     const float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    // power-of-two scales (exact divisions; the e4m3 matrix core applies them
+    // as block scales): e4m3 the power of two with amax / s in (224, 448]
+    // (448 = 0.875 * 2^9), bf16 2^ceil(log2 amax)
     float s = 1.f;
     if (amax > 0.f) {
+        int e;
+        const float f = frexpf(amax, &e);  // amax = f * 2^e, 0.5 <= f < 1
         if (dtype == TGEMM_FP8_E4M3) {
-            s = amax / 448.f;
+            e = f <= 0.875f ? e - 9 : e - 8;
+            s = ldexpf(1.f, e < -126 ? -126 : (e > 127 ? 127 : e));
         } else {
-            int e;
-            const float f = frexpf(amax, &e);         // amax = f * 2^e, 0.5 <= f < 1
-            s = ldexpf(1.f, f == 0.5f ? e - 1 : e);   // 2^ceil(log2 amax)
+            s = ldexpf(1.f, f == 0.5f ? e - 1 : e);
         }
     }
     if (t == 0) S[tile] = s;

@@ -377,8 +377,12 @@ __device__ __forceinline__ void pk_load(const char* stage, PkOps<CF>& o, int g, 
     }
 }
 
+// e4m3: sa8, sb8 are the matrix core's block scales of A and B (E8M0: byte
+// e means 2^(e - 127), the same as a float32's biased exponent field), the
+// same for every lane.  Constant zeros select the instruction without scales.
 template <class CF>
-__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN])
+__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN], int sa8 = 0,
+                                           int sb8 = 0)
 {
     if (CF::MODE == MODE_F32) {
         // element e of a lane's unit is k = 4*(2g + lane/32) + e for both
@@ -406,8 +410,8 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
                                  (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
                 const i32x8 y = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
                                  (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
-                // format codes 0/0: both operands OCP e4m3; no block scaling
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[i][j], 0, 0, 0, 0, 0, 0);
+                // format codes 0/0: both operands OCP e4m3
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[i][j], 0, 0, 0, sa8, 0, sb8);
             }
     } else {
         if (CF::MODE == MODE_X3) {
@@ -449,9 +453,10 @@ struct PackedOps {
     {
         pk_load<CF>(stage, o, g, wm0, wn0, lane);
     }
-    __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN])
+    __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN], int sa8 = 0,
+                                                   int sb8 = 0)
     {
-        pk_compute<CF>(o, acc);
+        pk_compute<CF>(o, acc, sa8, sb8);
     }
 };
 
@@ -466,9 +471,11 @@ struct NoIssue {
 // the next panel's loads there, so the reads do not queue behind them);
 // `before_last` runs before the last group's MFMAs, whose operands are the
 // last LDS reads of the stage (the caller may refill the stage from there).
-template <class CF, class OP = PackedOps<CF>, class F = NoIssue, class G = NoIssue>
+// MX: the e4m3 MFMAs take the block scales (sa8, sb8); otherwise none.
+template <class CF, class OP = PackedOps<CF>, bool MX = false, class F = NoIssue, class G = NoIssue>
 __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
-                                       int wn0, int lane, const F& then = F(), const G& before_last = G())
+                                       int wn0, int lane, const F& then = F(), const G& before_last = G(),
+                                       int sa8 = 0, int sb8 = 0)
 {
     constexpr int NREAD = OP::NREAD;
     constexpr int NMFMA = OP::NMFMA;
@@ -479,7 +486,8 @@ __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][
     for (int g = 0; g < CF::NG; ++g) {
         if (g + 1 < CF::NG) OP::load(stage, ops[(g + 1) & 1], g + 1, wm0, wn0, lane);
         else before_last();
-        OP::compute(ops[g & 1], acc);
+        if constexpr (MX) OP::compute(ops[g & 1], acc, sa8, sb8);
+        else OP::compute(ops[g & 1], acc);
         if (g + 1 < CF::NG) {
             // one LDS read between consecutive MFMAs while both last
 #pragma unroll
@@ -491,15 +499,41 @@ __device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][
     }
 }
 
-// Scale product of block (row0, col0) for K scale block kb.  (The loads are
-// vector loads, counted by vmcnt like the panel loads: packed_tile issues
-// them one panel ahead of their use.)
-__device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int col0, int kb)
+// Scales of A's and B's tiles for block (row0, col0) and K scale block kb.
+// (The loads are vector loads, counted by vmcnt like the panel loads:
+// packed_tile issues them one panel ahead of their use.)
+__device__ __forceinline__ void block_scales(const PackedArgs& a, int row0, int col0, int kb, float& sa,
+                                             float& sb)
 {
-    if (row0 >= a.M || col0 >= a.N) return 1.f;  // a block of padding: never stored
+    if (row0 >= a.M || col0 >= a.N) {  // a block of padding: never stored
+        sa = sb = 1.f;
+        return;
+    }
     const int64_t ia = __builtin_amdgcn_readfirstlane((int)((row0 / 128) * a.lds_a + kb));
     const int64_t ib = __builtin_amdgcn_readfirstlane((int)(kb * a.lds_b + col0 / 128));
-    return a.sA[ia] * a.sB[ib];
+    sa = a.sA[ia];
+    sb = a.sB[ib];
+}
+__device__ __forceinline__ float block_scale(const PackedArgs& a, int row0, int col0, int kb)
+{
+    float sa, sb;
+    block_scales(a, row0, col0, kb, sa, sb);
+    return sa * sb;
+}
+
+// A float32 scale s as 2^(e8 - 127) * m with e8 its biased exponent (the E8M0
+// byte the e4m3 matrix core applies exactly) and m in [1, 2) (sign kept);
+// zero, subnormal and non-finite s keep everything in m (e8 = 127: 2^0).
+__device__ __forceinline__ void split_scale(float s, int& e8, float& m)
+{
+    const uint32_t u = __float_as_uint(s), ex = (u >> 23) & 0xffu;
+    if (ex == 0u || ex == 0xffu) {
+        e8 = 127;
+        m = s;
+    } else {
+        e8 = (int)ex;
+        m = __uint_as_float((u & 0x807fffffu) | (127u << 23));
+    }
 }
 
 // A-side panel loads over packed rows of A (a.A, and a.Alo for x3): the
@@ -635,10 +669,6 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
         bl.issue(p0 + panel, stage + CF::NARR * CF::LDS_A);
     };
 
-    // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
-    constexpr int NS = CF::NS, L = AL::LOADS + BL::LOADS;
-    static_assert((NS - 2) * L <= 63, "vmcnt holds at most 63");
-    for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
     // Scaled forms: acc is kept divided by the scale product of the current K
     // block (128 deep).  The products of the next block are loaded one panel
     // ahead, before that panel's successor is issued, so the waits of the panel
@@ -649,15 +679,46 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
     // start at multiples of their size), so one product serves all its blocks.
     constexpr bool one_scale = CF::WTM <= 128 && CF::WTN <= 128;
     constexpr int SM = one_scale ? 1 : CF::TM, SN = one_scale ? 1 : CF::TN;
+    // e4m3 with one product per wave: the powers of two of sA and sB go to the
+    // matrix core as its block scales (e8a, e8b), and acc is kept in units of
+    // the product of their mantissas, m = fl32(ma * mb) = fl32(sA * sB) / 2^E;
+    // with power-of-two scales m stays 1 and acc is never rescaled.
+    constexpr bool mx = scaled && one_scale && CF::MODE == MODE_FP8;
     int kb_cur = (p0 * CF::BK) / 128;
-    float sc_cur[SM][SN], sc_next[SM][SN];
+    float sc_cur[SM][SN], sc_next[SM][SN];  // mx: sc_cur holds m, sc_next the raw sB
+    int e8a = 127, e8b = 127;
+    float sa_next = 1.f;
     auto load_scales = [&](int kb, float (&dst)[SM][SN]) {
+        if constexpr (mx) {
+            block_scales(a, m0 + wm0, n0 + wn0, kb, sa_next, dst[0][0]);
+        } else {
 #pragma unroll
-        for (int i = 0; i < SM; ++i)
+            for (int i = 0; i < SM; ++i)
 #pragma unroll
-            for (int j = 0; j < SN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
+                for (int j = 0; j < SN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
+        }
     };
-    if (scaled) load_scales(kb_cur, sc_cur);
+    // the unit of the block whose raw scales are sa_next and sc_next (mx)
+    auto mx_unit = [&](int& ea, int& eb) {
+        float ma, mb;
+        split_scale(sa_next, ea, ma);
+        split_scale(sc_next[0][0], eb, mb);
+        return ma * mb;
+    };
+    // issued before the first panels, so the first panel's wait covers them
+    if constexpr (scaled) {
+        if constexpr (mx) {
+            load_scales(kb_cur, sc_next);
+        } else {
+            load_scales(kb_cur, sc_cur);
+        }
+    }
+
+    // Pipeline: panels p go to stage p % NS; NS - 1 panels are in flight.
+    constexpr int NS = CF::NS, L = AL::LOADS + BL::LOADS;
+    static_assert((NS - 2) * L <= 63, "vmcnt holds at most 63");
+    for (int p = 0; p < NS - 1 && p < npanel; ++p) issue(p, lds + p * CF::LDS_STAGE);
+    bool first_block = true;  // mx: the unit of the first block is set at its first panel
     auto prefetch = [&](int s) {  // during panel s: the scales of panel s + 1 if it opens a block
         if (!scaled || s + 1 >= npanel) return;
         const int kb = ((p0 + s + 1) * CF::BK) / 128;
@@ -667,6 +728,27 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
     auto rescale = [&](int s) {
         if (!scaled) return;
         const int kb = ((p0 + s) * CF::BK) / 128;
+        if constexpr (mx) {
+            if (first_block) {
+                first_block = false;
+                sc_cur[0][0] = mx_unit(e8a, e8b);
+                return;
+            }
+            if (kb == kb_cur) return;
+            const float m = mx_unit(e8a, e8b);
+            const float ratio = sc_cur[0][0] / m;
+            if (ratio != 1.f) {
+#pragma unroll
+                for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < CF::TN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+            }
+            sc_cur[0][0] = m;
+            kb_cur = kb;
+            return;
+        }
         if (s == 0 || kb == kb_cur) return;
         if constexpr (one_scale) {
             // one product per wave: nothing to do when it does not change (acc * 1 == acc)
@@ -715,11 +797,11 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
             rescale(s);   // consumes the scales prefetched during panel s - 1 ...
             prefetch(s);  // ... before they are replaced by those of panel s + 1
             char* stage = lds + (s % NS) * CF::LDS_STAGE;
-            pk_mma<CF, OP>(stage, acc, wm0, wn0, lane, NoIssue(), [&] {
+            pk_mma<CF, OP, mx>(stage, acc, wm0, wn0, lane, NoIssue(), [&] {
                 wait_lds_reads();  // this wave's reads of the stage are done ...
                 lds_barrier();     // ... and every wave's: the stage is free
                 if (s + 2 < npanel) issue(s + 2, stage);
-            });
+            }, e8a, e8b);
         }
     } else if constexpr (NS == 2) {
         for (int s = 0; s < npanel; ++s) {
@@ -738,10 +820,11 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
                 if (s + NS - 1 < npanel) issue(s + NS - 1, lds + ((s + NS - 1) % NS) * CF::LDS_STAGE);
             };
             if constexpr (CF::BM >= 256 && CF::BN >= 256) {
-                pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane, next);
+                pk_mma<CF, OP, mx>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane, next, NoIssue(), e8a, e8b);
             } else {
                 next();
-                pk_mma<CF, OP>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane);
+                pk_mma<CF, OP, mx>(lds + (s % NS) * CF::LDS_STAGE, acc, wm0, wn0, lane, NoIssue(), NoIssue(), e8a,
+                                   e8b);
             }
         }
     } else {
@@ -777,7 +860,8 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
                     OP::load(lds + ((s + 1) % NS) * CF::LDS_STAGE, ops[CF::NG & 1], 0, wm0, wn0, lane);
                     read = true;
                 }
-                OP::compute(ops[g & 1], acc);
+                if constexpr (mx) OP::compute(ops[g & 1], acc, e8a, e8b);
+                else OP::compute(ops[g & 1], acc);
                 if (read) {
 #pragma unroll
                     for (int k = 0; k < NPAIR; ++k) {
