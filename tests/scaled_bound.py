@@ -5,7 +5,11 @@ The kernel computes C = alpha * sum_b s_b * sum_{k in b} qA[i,k] qB[k,j] over K
 blocks b of 128, with s_b = fl32(sA[i/128, b] * sB[b, j/128]).  Its running sum
 acc is a float32 kept in units of the current block's scale product: at a block
 change acc <- fl32(acc * fl32(s_prev / s_cur)), at the end
-C = fl32(fl32(alpha * s_last) * acc).  Every term therefore passes through at
+C = fl32(fl32(alpha * s_last) * acc).  (The e4m3 kernels let the matrix
+instruction apply the power-of-two part 2^E of s_b exactly and keep acc in
+units of its mantissa part m_b = s_b / 2^E; every rounding above then happens
+on values scaled by powers of two, so the same bound holds, and with
+power-of-two scales the rescale never happens.)  Every term therefore passes through at
 most n = (additions into acc) + 3 per block + 3 float32 roundings, each of
 relative size at most u = 2^-24, which bounds the float32 part of the error by
 n * u * sum_k |s_b qA qB| (to first order; the 1.001 factor covers the rest).
