@@ -381,8 +381,8 @@ const char* tgemm_status_string(int status);
 int tgemm_set_policy(const char* policy);
 
 /* Number of compiled schedules and the parameters of one of them.
- * info receives 9 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes,
- * split.
+ * info receives 10 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes,
+ * split, mfma.
  * vec = 4: 16-byte global loads (16-byte aligned bases, row strides multiple of
  * 16 bytes); vec = 1: 4-byte loads (any alignment); vec = 0: packed operands
  * (a pre-pass copies A and B^T, converted and zero-padded, into a workspace
@@ -393,6 +393,9 @@ int tgemm_set_policy(const char* policy);
  * from partial sums in the stream's workspace (2 * slots * BM * BN floats more)
  * and per-tile counters (4 MiB per device and stream, allocated on first use).
  * split = 0: one workgroup per tile.
+ * mfma = 32: the MFMAs compute 32 x 32 output blocks (v_mfma_f32_32x32x2f32,
+ * 32x32x16_bf16, 32x32x64_f8f6f4); mfma = 16: 16 x 16 blocks (16x16x4f32,
+ * 16x16x32_bf16, 16x16x128_f8f6f4; packed schedules only).
  * Host-only: no HIP call. */
 int tgemm_schedule_count(void);
 int tgemm_schedule_info(int schedule_id, int* info);
@@ -465,7 +468,7 @@ int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m,
                     int64_t step, float lr, void* stream);
 
 /*
- * Learned cost model (project addition).  A 21-feature ReLU MLP (3 hidden
+ * Learned cost model (project addition).  A 22-feature ReLU MLP (3 hidden
  * layers of 256) predicts the log runtime of (problem, schedule, tile order).
  *
  * tgemm_costmodel_train: reads the valid records of a tuning database written
@@ -489,7 +492,7 @@ int tgemm_adam_step(int64_t n, float* params, const float* grads, float* adam_m,
  * tgemm_costmodel_select: the prediction when the model can answer, else
  *   exhaustive autotuning (tgemm_autotune with `reps`, appending to db_path);
  *   *used_fallback says which.
- * tgemm_costmodel_features: the feature vector (21 floats, host) of one
+ * tgemm_costmodel_features: the feature vector (22 floats, host) of one
  *   candidate.  Host-only.
  */
 int tgemm_costmodel_train(const char* db_path, const char* weights_out, int epochs, int batch,

@@ -289,6 +289,7 @@ int tgemm_schedule_info(int id, int* info)
     info[6] = d.vec;
     info[7] = d.lds_bytes;
     info[8] = d.split;
+    info[9] = d.mfma;
     return TGEMM_SUCCESS;
 }
 

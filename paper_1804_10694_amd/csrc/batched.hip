@@ -32,6 +32,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tgemm.h"
@@ -116,6 +117,16 @@ constexpr int kInplaceOcc = (160 * 1024) / GroupInplace<MODE>::LDS_BYTES > kInpl
                                 ? kInplaceCap<MODE>
                                 : (160 * 1024) / GroupInplace<MODE>::LDS_BYTES;
 constexpr int kInplaceTile = 64;
+// In-place 128 x 128 tiles for the problems whose M and N reach the plan's
+// tile threshold: 4 waves of 64 x 64, the same 16-deep panels in two 16 KB
+// stages; four workgroups per CU (x3: three, for the registers of its operand
+// split).  Each panel byte feeds twice the MFMAs of a 64 x 64 tile, which
+// halves the operand reads from L2 and beyond.
+template <int MODE>
+using GroupInplace128 = ICfg<MODE, 128, 128, 16, 2, 2, 2>;
+template <int MODE>
+constexpr int kInplace128Occ = (MODE == MODE_F32) ? 4 : 3;
+constexpr int kInplace128Tile = 128;
 
 template <class CF>
 __device__ __forceinline__ void run_tile(const GemmArgs& a, int local, char* lds)
@@ -258,12 +269,14 @@ __global__ void __launch_bounds__(256) small_batched_kernel(SmallArgs a)
     }
 }
 
-// Persistent kernel of the in-place class.
-template <int MODE>
-__global__ void __launch_bounds__(GroupInplace<MODE>::NT, kInplaceOcc<MODE>)
+// Persistent kernels of the in-place classes (64 x 64 and 128 x 128 tiles).
+template <int MODE, int T>
+using InplaceCfgOf = typename std::conditional<T == 64, GroupInplace<MODE>, GroupInplace128<MODE>>::type;
+template <int MODE, int T>
+__global__ void __launch_bounds__((InplaceCfgOf<MODE, T>::NT), (T == 64 ? kInplaceOcc<MODE> : kInplace128Occ<MODE>))
     grouped_inplace_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, int total)
 {
-    using CF = GroupInplace<MODE>;
+    using CF = InplaceCfgOf<MODE, T>;
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int2 pl = map[t];  // (problem, tile within it)
@@ -362,7 +375,7 @@ struct Plan {
     int dtype = 0;
     int device = -1;
     GroupDesc* d_desc = nullptr;
-    Space pack, packed, inplace, direct;  // packing pass, packed, in-place and direct class tiles
+    Space pack, packed, inplace128, inplace, direct;  // packing pass, packed, in-place (128, 64), direct
     bool mixed = false;          // the direct class has 128 x 128 tiles
     char* ws = nullptr;          // packed operands
 };
@@ -409,9 +422,9 @@ bool reaches(const GroupDesc& g, int t) { return g.M >= t && g.N >= t; }
 // Whether a direct-class problem with 64 x 64 tiles can take the in-place
 // tiles: a tile's rows of A and a panel's rows of B within the 32-bit reach of
 // a buffer offset.
-bool inplace_ok(const GroupDesc& g)
+bool inplace_ok(const GroupDesc& g, int tile)
 {
-    return (int64_t)kInplaceTile * g.lda * 4 <= INT32_MAX &&
+    return (int64_t)tile * g.lda * 4 <= INT32_MAX &&
            (int64_t)GroupInplace<MODE_F32>::BK * g.ldb * 4 <= INT32_MAX &&
            (int64_t)GroupInplace<MODE_X3>::BK * g.ldb * 4 <= INT32_MAX;
 }
@@ -455,9 +468,9 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
                const int64_t* ldb, const float* beta, float* const* C, const int64_t* ldc, int dtype,
                Shape shape, Plan* plan)
 {
-    // packed problems first, then the in-place ones, then the direct ones;
-    // heaviest tiles first in each class
-    enum { kDirect = 0, kPacked = 1, kInplace = 2 };
+    // packed problems first, then the in-place ones (128 x 128 tiles, then
+    // 64 x 64), then the direct ones; heaviest tiles first in each class
+    enum { kDirect = 0, kPacked = 1, kInplace = 2, kInplace128 = 3 };
     std::vector<GroupDesc> descs;
     std::vector<char> cls;
     for (int64_t p = 0; p < count; ++p) {
@@ -489,10 +502,10 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         g.tiles_m = (int)((M[p] + t - 1) / t);
         g.tiles_n = (int)((N[p] + t - 1) / t);
         char c = pk ? kPacked : kDirect;
-        if (!pk && !g.scale_only && g.cfg < 2 && inplace_ok(g)) {
-            c = kInplace;
+        if (!pk && !g.scale_only && inplace_ok(g, t)) {
+            c = g.cfg < 2 ? kInplace : kInplace128;
             // 16-byte units need aligned rows and no unit across the end of a row
-            g.ip_vec = (g.cfg == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
+            g.ip_vec = ((g.cfg & 1) == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
         }
         descs.push_back(g);
         cls.push_back(c);
@@ -502,10 +515,13 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     auto work = [&](size_t i) {
         const GroupDesc& g = descs[i];
         if (g.scale_only) return 0.0;
-        const double t = cls[i] == kPacked ? kPackedTile : cls[i] == kInplace ? kInplaceTile : kGroupTile[g.cfg];
+        const double t = cls[i] == kPacked ? kPackedTile : cls[i] == kInplace ? kInplaceTile
+                         : cls[i] == kInplace128 ? kInplace128Tile : kGroupTile[g.cfg];
         return t * t * g.K;
     };
-    auto rank = [&](size_t i) { return cls[i] == kPacked ? 0 : cls[i] == kInplace ? 1 : 2; };
+    auto rank = [&](size_t i) {
+        return cls[i] == kPacked ? 0 : cls[i] == kInplace128 ? 1 : cls[i] == kInplace ? 2 : 3;
+    };
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
         if (rank(x) != rank(y)) return rank(x) < rank(y);
         return work(x) > work(y);
@@ -527,14 +543,19 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     const int64_t arrays = dtype == TGEMM_F32_BF16X3 ? 2 : 1, esz = 4 / arrays;
     int64_t off = 0;
     std::vector<int64_t> offs(descs.size(), 0);
-    std::vector<int> pack_units, packed_tiles, inplace_tiles, direct_tiles;
-    std::vector<int> pack_owner, packed_owner, inplace_owner, direct_owner;
+    std::vector<int> pack_units, packed_tiles, inplace128_tiles, inplace_tiles, direct_tiles;
+    std::vector<int> pack_owner, packed_owner, inplace128_owner, inplace_owner, direct_owner;
     for (size_t i = 0; i < descs.size(); ++i) {
         GroupDesc& g = descs[i];
         const int tiles = g.tiles_m * g.tiles_n;
         if (cls[i] == kInplace) {
             inplace_tiles.push_back(tiles);
             inplace_owner.push_back((int)i);
+            continue;
+        }
+        if (cls[i] == kInplace128) {
+            inplace128_tiles.push_back(tiles);
+            inplace128_owner.push_back((int)i);
             continue;
         }
         if (cls[i] == kDirect) {
@@ -574,6 +595,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     int rc;
     if ((rc = upload_map(pack_units, pack_owner, &plan->pack)) != TGEMM_SUCCESS) return rc;
     if ((rc = upload_map(packed_tiles, packed_owner, &plan->packed)) != TGEMM_SUCCESS) return rc;
+    if ((rc = upload_map(inplace128_tiles, inplace128_owner, &plan->inplace128)) != TGEMM_SUCCESS) return rc;
     if ((rc = upload_map(inplace_tiles, inplace_owner, &plan->inplace)) != TGEMM_SUCCESS) return rc;
     if ((rc = upload_map(direct_tiles, direct_owner, &plan->direct)) != TGEMM_SUCCESS) return rc;
     const bool f32 = dtype == TGEMM_F32;
@@ -582,8 +604,11 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     plan->packed.grid = resident_grid(f32 ? (const void*)&grouped_packed_kernel<MODE_F32>
                                           : (const void*)&grouped_packed_kernel<MODE_X3>,
                                       GroupPacked<MODE_F32>::NT, plan->packed.total);
-    plan->inplace.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32>
-                                           : (const void*)&grouped_inplace_kernel<MODE_X3>,
+    plan->inplace128.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 128>
+                                              : (const void*)&grouped_inplace_kernel<MODE_X3, 128>,
+                                          GroupInplace128<MODE_F32>::NT, plan->inplace128.total);
+    plan->inplace.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 64>
+                                           : (const void*)&grouped_inplace_kernel<MODE_X3, 64>,
                                        GroupInplace<MODE_F32>::NT, plan->inplace.total);
     for (size_t i = 0; i < descs.size(); ++i)
         plan->mixed = plan->mixed || (cls[i] == kDirect && !descs[i].scale_only && descs[i].cfg >= 2);
@@ -601,7 +626,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
 
 void free_plan(Plan& p)
 {
-    for (Space* sp : {&p.pack, &p.packed, &p.inplace, &p.direct}) {
+    for (Space* sp : {&p.pack, &p.packed, &p.inplace128, &p.inplace, &p.direct}) {
         if (sp->d_map) (void)hipFree(sp->d_map);
         sp->d_map = nullptr;
     }
@@ -620,9 +645,12 @@ void launch_modes(const Plan& p, hipStream_t s)
     if (p.packed.total > 0)
         hipLaunchKernelGGL(grouped_packed_kernel<MODE>, dim3(p.packed.grid), dim3(GroupPacked<MODE>::NT), 0,
                            s, p.d_desc, p.packed.d_map, p.packed.total);
+    if (p.inplace128.total > 0)
+        hipLaunchKernelGGL((grouped_inplace_kernel<MODE, 128>), dim3(p.inplace128.grid),
+                           dim3(GroupInplace128<MODE>::NT), 0, s, p.d_desc, p.inplace128.d_map, p.inplace128.total);
     if (p.inplace.total > 0)
-        hipLaunchKernelGGL(grouped_inplace_kernel<MODE>, dim3(p.inplace.grid), dim3(GroupInplace<MODE>::NT), 0,
-                           s, p.d_desc, p.inplace.d_map, p.inplace.total);
+        hipLaunchKernelGGL((grouped_inplace_kernel<MODE, 64>), dim3(p.inplace.grid), dim3(GroupInplace<MODE>::NT),
+                           0, s, p.d_desc, p.inplace.d_map, p.inplace.total);
     if (p.direct.total > 0 && p.mixed)
         hipLaunchKernelGGL((grouped_kernel<MODE, true>), dim3(p.direct.grid), dim3(256), 0, s, p.d_desc,
                            p.direct.d_map, p.direct.total);

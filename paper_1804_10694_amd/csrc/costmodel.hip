@@ -37,14 +37,14 @@ bool vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int dtype);
 
 namespace {
 
-constexpr int kFeatures = 21;
+constexpr int kFeatures = 22;
 constexpr int kHidden = 256;
 constexpr int kLayers = 4;  // 3 hidden layers of 256, one output
 const int kDims[kLayers + 1] = {kFeatures, kHidden, kHidden, kHidden, 1};
 constexpr uint32_t kMagic = 0x4d434754u;  // "TGCM"
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 // Tile-order variants the model ranks (the autotuner's set).
-const int kVariants[][2] = {{1, 0}, {4, 1}, {8, 1}, {16, 1}};
+const int kVariants[][2] = {{1, 0}, {4, 0}, {8, 0}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {32, 1}};
 // A shape is out of distribution when a log2 dimension lies this far outside
 // the training range.
 constexpr float kOodMargin = 0.5f;
@@ -87,6 +87,7 @@ void cost_features(int64_t M, int64_t N, int64_t K, int dtype, const SchedDesc& 
     f[i++] = (float)lg2(kpanels);
     f[i++] = (float)d.lds_bytes / (160.f * 1024.f);
     f[i++] = (float)d.split;                                        // stream-K
+    f[i++] = d.mfma == 16 ? 1.f : 0.f;                              // 16 x 16 MFMA blocks
 }
 
 namespace {

@@ -114,11 +114,11 @@ struct SkPartial {
     // wave covers 256 contiguous bytes.
     __device__ __forceinline__ static int elem(int wave, int i, int j, int r, int lane)
     {
-        return (((wave * CF::TM + i) * CF::TN + j) * 16 + r) * 64 + lane;
+        return (((wave * CF::TM + i) * CF::TN + j) * CF::AR + r) * 64 + lane;
     }
 
     template <class SC>
-    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+    __device__ __forceinline__ void operator()(typename CF::Acc (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
                                                int wn0, int lane) const
     {
         asm volatile("" : "+v"(lane));  // keep the slot addresses out of the main loop
@@ -130,7 +130,7 @@ struct SkPartial {
             for (int j = 0; j < CF::TN; ++j) {
                 const float f = sc(i, j);
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
+                for (int r = 0; r < CF::AR; ++r)
                     __hip_atomic_store(mine + elem(wave, i, j, r, lane), f * acc[i][j][r], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -147,16 +147,15 @@ struct SkPartial {
         if (!*flag) return;
         // sum every range's partial (this one's included, read back) in K order,
         // four sums at a time
-        const int h = lane >> 5, l32 = lane & 31;
         const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
         const bool read_c = (a.beta != 0.f);
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j) {
-                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+                const int r0 = m0 + wm0 + CF::MS * i, c0 = n0 + wn0 + CF::MS * j;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < CF::AR / 4; ++q) {
                     f32x4 s4 = {0.f, 0.f, 0.f, 0.f};
                     for (int u = u0; u <= u1; ++u) {
                         const float* src = slot(u);
@@ -168,8 +167,8 @@ struct SkPartial {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int r = 4 * q + e;
-                        const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
-                        const int col = c0 + l32;
+                        const int row = r0 + CF::out_row(r, lane);
+                        const int col = c0 + CF::out_col(lane);
                         if (!full && (row >= a.M || col >= a.N)) continue;
                         float* pc = a.C + (int64_t)row * a.ldc + col;
                         float val = a.alpha * s4[e];
@@ -187,7 +186,7 @@ struct SkStore {
     SkPartial<CF> part;
     bool is_whole;
     template <class SC>
-    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+    __device__ __forceinline__ void operator()(typename CF::Acc (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
                                                int wn0, int lane) const
     {
         if (is_whole) whole(acc, sc, wm0, wn0, lane);
@@ -233,17 +232,23 @@ struct PSched {
     int dtype, mode, BM, BN, BK, WGM, WGN, lds, threads;
     void (*kernel)(PackedArgs);
     void (*sk_kernel)(PackedArgs, SkArgs);  // stream-K form, or null
+    int mfma;                               // MFMA block (32 or 16)
 };
 
 #define TG_PSCHED(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                             \
     {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::LDS_BYTES,              \
      PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>, \
-     nullptr}
+     nullptr, 32}
 // A schedule that also has a stream-K form (a second registry entry).
 #define TG_PSCHED_SK(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                          \
     {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::LDS_BYTES,              \
      PCfg<MODE, BM, BN, BK, WGM, WGN, NS>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>, \
-     &packed_sk_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>}
+     &packed_sk_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS>>, 32}
+// A schedule on 16 x 16 MFMA blocks.
+#define TG_PSCHED16(DT, MODE, BM, BN, BK, WGM, WGN, NS)                                               \
+    {DT, MODE, BM, BN, BK, WGM, WGN, PCfg<MODE, BM, BN, BK, WGM, WGN, NS, 16>::LDS_BYTES,              \
+     PCfg<MODE, BM, BN, BK, WGM, WGN, NS, 16>::NT, &packed_kernel<PCfg<MODE, BM, BN, BK, WGM, WGN, NS, 16>>, \
+     nullptr, 16}
 
 constexpr PSched kPacked[] = {
     // two workgroups per CU (LDS <= 80 KB), 4 waves each
@@ -274,6 +279,16 @@ constexpr PSched kPacked[] = {
     TG_PSCHED_SK(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 4, 2, 2),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 64, 2, 4, 4),
     TG_PSCHED(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2, 2),
+    // 16 x 16 MFMA blocks (v_mfma_f32_16x16x4f32, 16x16x32_bf16, 16x16x128_f8f6f4)
+    TG_PSCHED16(TGEMM_F32, MODE_F32, 128, 256, 32, 4, 2, 2),
+    TG_PSCHED16(TGEMM_F32, MODE_F32, 128, 128, 16, 2, 2, 2),
+    TG_PSCHED16(TGEMM_F32, MODE_F32, 256, 256, 32, 2, 4, 2),
+    TG_PSCHED16(TGEMM_F32_BF16X3, MODE_X3, 128, 128, 32, 2, 2, 2),
+    TG_PSCHED16(TGEMM_F32_BF16X3, MODE_X3, 256, 128, 32, 2, 4, 3),
+    TG_PSCHED16(TGEMM_BF16, MODE_BF16, 256, 256, 64, 2, 4, 2),
+    TG_PSCHED16(TGEMM_BF16, MODE_BF16, 128, 128, 64, 2, 2, 2),
+    TG_PSCHED16(TGEMM_FP8_E4M3, MODE_FP8, 256, 256, 128, 4, 2, 2),
+    TG_PSCHED16(TGEMM_FP8_E4M3, MODE_FP8, 128, 128, 128, 2, 2, 2),
 };
 constexpr int kNumPacked = sizeof(kPacked) / sizeof(kPacked[0]);
 constexpr int count_sk()
@@ -297,6 +312,7 @@ struct DescInit {
             const PSched& p = kPacked[i];
             g_packed_desc[i] = SchedDesc{p.dtype, p.BM, p.BN, p.BK, p.WGM, p.WGN, 0, p.lds, p.threads,
                                          nullptr};
+            g_packed_desc[i].mfma = p.mfma;
             if (p.sk_kernel) {
                 g_packed_desc[kNumPacked + n] = g_packed_desc[i];
                 g_packed_desc[kNumPacked + n].split = 1;

@@ -17,6 +17,7 @@ struct SchedDesc {
     void (*kernel)(GemmArgs);
     int split = 0;  // 1: stream-K (packed schedules): the (tile, K panel) iterations are split
                     // evenly over one wave of resident workgroups
+    int mfma = 32;  // MFMA block: 32 (32 x 32 outputs) or 16 (16 x 16)
 };
 
 // All compiled schedules, ids 0..num_schedules()-1 (tables of every kernel

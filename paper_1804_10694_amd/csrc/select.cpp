@@ -110,12 +110,13 @@ bool dense_vec_ok(int64_t N, int64_t K, int dtype)
     return (K * es) % 16 == 0 && (N * es) % 16 == 0;
 }
 
-int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds)
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds, int mfma)
 {
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec &&
-            d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds))
+            d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds) && d.split == 0 &&
+            d.mfma == mfma)
             return i;
     }
     return -1;
@@ -173,10 +174,14 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    each), 1317 TFLOP/s at 16384^3 against 1266 with waves 2 x 4 and
     //    1195 for 128 x 128 tiles of four workgroups per CU (which it takes
     //    below that size).
+    //  - f32 with 256 to 383 tiles of 128 x 256 (half to three quarters of a
+    //    wave at two workgroups per CU): 128 x 128 tiles on 16 x 16 MFMA blocks,
+    //    four workgroups per CU (3000^3: 0.59 ms against 0.73 for 128 x 256).
     if (K >= 512 && packed_k_ok(K, dtype)) {
         int id = -1;
         if (dtype == TGEMM_F32) {
-            if (tiles(128, 256) >= 256) id = find_schedule(dtype, 128, 256, 16, 0, 4, 2);
+            if (tiles(128, 256) >= 384) id = find_schedule(dtype, 128, 256, 16, 0, 4, 2);
+            else if (tiles(128, 256) >= 256) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 32768, 16);
             else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
         } else if (dtype == TGEMM_FP8_E4M3) {
             if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, 128, 0, 4, 2);

@@ -29,7 +29,8 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
 int direct_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out);
 
 // Index of the compiled schedule with these parameters, or -1.
-int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM = 2, int WGN = 2, int lds = -1);
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM = 2, int WGN = 2, int lds = -1,
+                  int mfma = 32);
 
 // Tuned choices (filled by the autotuner and by the database loader).
 void register_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, const Choice& c, double ms);

@@ -46,6 +46,10 @@ struct ICfg {
     static constexpr int HS = MK / 2;                          // k offset of lanes 32..63
     static constexpr int NG = BK / MK;
     static constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 32, TN = WTN / 32;
+    static constexpr int MS = 32, AR = 16;                     // 32 x 32 MFMA blocks
+    using Acc = f32x16;
+    __device__ __forceinline__ static int out_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    __device__ __forceinline__ static int out_col(int lane) { return lane & 31; }
     static constexpr int NARR = 1;                             // float32 in LDS for both forms
     static constexpr int LDS_A = BM * BK * 4, LDS_B = BK * BN * 4;
     static constexpr int LDS_STAGE = LDS_A + LDS_B;

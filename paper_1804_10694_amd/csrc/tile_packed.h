@@ -231,20 +231,32 @@ __device__ __forceinline__ void pack_col_block(const void* X, int64_t ldx, int K
 }
 
 // ------------------------------------------------------------------ main loop
-template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_>
+// MS: the MFMA block (32: 32 x 32 outputs, 16 per lane; 16: 16 x 16, 4 per lane).
+template <int MODE_, int BM_, int BN_, int BK_, int WGM_, int WGN_, int NS_, int MS_ = 32>
 struct PCfg {
     static constexpr int MODE = MODE_, BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
     static constexpr int NS = NS_;  // LDS stages (panels in flight = NS - 1)
+    static constexpr int MS = MS_;
+    static constexpr int LG = 64 / MS;                   // lane groups along k of one MFMA
+    static constexpr int AR = MS * MS / 64;              // accumulator registers per lane per block
+    using Acc = typename std::conditional<MS == 32, f32x16, f32x4>::type;
     static constexpr int ES = (MODE == MODE_FP8) ? 1 : (MODE == MODE_F32) ? 4 : 2;  // bytes
     static constexpr int NT = 64 * WGM * WGN, NW = WGM * WGN;
     static constexpr int KU = 16 / ES;                   // k per 16-byte unit
     static constexpr int UK = BK / KU;                   // units per packed row per panel
-    // k per MFMA group: 32x32x64 e4m3, 32x32x16 bf16; f32 runs the four
-    // 32x32x2 MFMAs of one unit per lane as a group of 8 k
-    static constexpr int MK = (MODE == MODE_FP8) ? 64 : (MODE == MODE_F32) ? 8 : 16;
-    static constexpr int UPL = MK / KU / 2;              // units per lane per group
+    // units per lane per MFMA group: one (f32: the four 32x32x2 or 16x16x4 MFMAs
+    // of its four k; bf16 and x3: 8 k) or two (e4m3: 32 k); k per group MK:
+    // 32 x 32 blocks: f32 8, bf16 16, e4m3 64; 16 x 16: f32 16, bf16 32, e4m3 128
+    static constexpr int UPL = (MODE == MODE_FP8) ? 2 : 1;
+    static constexpr int MK = LG * UPL * KU;
     static constexpr int NG = BK / MK;
-    static constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / 32, TN = WTN / 32;
+    static constexpr int WTM = BM / WGM, WTN = BN / WGN, TM = WTM / MS, TN = WTN / MS;
+    // output row and column of accumulator register r of a block, for `lane`
+    __device__ __forceinline__ static int out_row(int r, int lane)
+    {
+        return MS == 32 ? 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3) : 4 * (lane >> 4) + r;
+    }
+    __device__ __forceinline__ static int out_col(int lane) { return lane & (MS - 1); }
     static constexpr int NARR = (MODE == MODE_X3) ? 2 : 1;
     static constexpr int LDS_A = BM * UK * 16, LDS_B = BN * UK * 16;
     static constexpr int LDS_STAGE = NARR * (LDS_A + LDS_B);
@@ -262,7 +274,8 @@ struct PCfg {
     static_assert(BK % MK == 0 && 128 % BK == 0, "panels tile K");
     static_assert((BM * UK) % (64 * NW) == 0 && (BN * UK) % (64 * NW) == 0, "loads divide among waves");
     static_assert(UK <= 16 && 16 % UK == 0, "swizzle");
-    static_assert(WTM % 32 == 0 && WTN % 32 == 0, "whole blocks");
+    static_assert(WTM % MS == 0 && WTN % MS == 0, "whole blocks");
+    static_assert(MS == 32 || MS == 16, "MFMA block");
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -358,34 +371,62 @@ template <class CF>
 __device__ __forceinline__ void pk_load(const char* stage, PkOps<CF>& o, int g, int wm0, int wn0,
                                         int lane)
 {
-    constexpr int UK = CF::UK, UPL = CF::UPL;
-    const int h = lane >> 5, l32 = lane & 31;
+    constexpr int UK = CF::UK, UPL = CF::UPL, MS = CF::MS;
+    const int h = lane / MS, l32 = lane & (MS - 1);  // lane group along k, row in the block
 #pragma unroll
     for (int v = 0; v < PkOps<CF>::AV; ++v) {
-        const int u = (2 * g + h) * UPL + v;
+        const int u = (CF::LG * g + h) * UPL + v;
 #pragma unroll
         for (int x = 0; x < PkOps<CF>::NA; ++x) {
             const char* la = stage + x * CF::LDS_A;
             const char* lb = stage + CF::NARR * CF::LDS_A + x * CF::LDS_B;
 #pragma unroll
             for (int i = 0; i < CF::TM; ++i)
-                o.a[x][i][v] = *reinterpret_cast<const u32x4*>(la + pk_slot<UK>(wm0 + 32 * i + l32, u) * 16);
+                o.a[x][i][v] = *reinterpret_cast<const u32x4*>(la + pk_slot<UK>(wm0 + MS * i + l32, u) * 16);
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j)
-                o.b[x][j][v] = *reinterpret_cast<const u32x4*>(lb + pk_slot<UK>(wn0 + 32 * j + l32, u) * 16);
+                o.b[x][j][v] = *reinterpret_cast<const u32x4*>(lb + pk_slot<UK>(wn0 + MS * j + l32, u) * 16);
         }
     }
+}
+
+// The MFMA of each form for either block size, chosen by the accumulator type
+// (f32x16: 32 x 32 blocks, f32x4: 16 x 16).
+__device__ __forceinline__ f32x16 mma_f32(float a, float b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// format codes 0/0: both operands OCP e4m3; sa8, sb8: block scales (E8M0)
+__device__ __forceinline__ f32x16 mma_fp8(i32x8 a, i32x8 b, f32x16 c, int sa8, int sb8)
+{
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa8, 0, sb8);
+}
+__device__ __forceinline__ f32x4 mma_fp8(i32x8 a, i32x8 b, f32x4 c, int sa8, int sb8)
+{
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa8, 0, sb8);
 }
 
 // e4m3: sa8, sb8 are the matrix core's block scales of A and B (E8M0: byte
 // e means 2^(e - 127), the same as a float32's biased exponent field), the
 // same for every lane.  Constant zeros select the instruction without scales.
 template <class CF>
-__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF::TM][CF::TN], int sa8 = 0,
-                                           int sb8 = 0)
+__device__ __forceinline__ void pk_compute(const PkOps<CF>& o, typename CF::Acc (&acc)[CF::TM][CF::TN],
+                                           int sa8 = 0, int sb8 = 0)
 {
     if (CF::MODE == MODE_F32) {
-        // element e of a lane's unit is k = 4*(2g + lane/32) + e for both
+        // element e of a lane's unit is k = 4*(LG g + lane group) + e for both
         // operands, so MFMA e pairs equal k in A and B.  (The elements are
         // copied out before the bit cast: a bit cast applied to a vector
         // element in place compiles to a read of element 0.)
@@ -396,8 +437,7 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
 #pragma unroll
                 for (int j = 0; j < CF::TN; ++j) {
                     const uint32_t xa = o.a[0][i][0][e], xb = o.b[0][j][0][e];
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                        __builtin_bit_cast(float, xa), __builtin_bit_cast(float, xb), acc[i][j], 0, 0, 0);
+                    acc[i][j] = mma_f32(__builtin_bit_cast(float, xa), __builtin_bit_cast(float, xb), acc[i][j]);
                 }
     } else if (CF::MODE == MODE_FP8) {
 #pragma unroll
@@ -410,8 +450,7 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
                                  (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
                 const i32x8 y = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
                                  (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
-                // format codes 0/0: both operands OCP e4m3
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, acc[i][j], 0, 0, 0, sa8, 0, sb8);
+                acc[i][j] = mma_fp8(x, y, acc[i][j], sa8, sb8);
             }
     } else {
         if (CF::MODE == MODE_X3) {
@@ -420,24 +459,21 @@ __device__ __forceinline__ void pk_compute(const PkOps<CF>& o, f32x16 (&acc)[CF:
             for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
                 for (int j = 0; j < CF::TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, o.a[PkOps<CF>::NA - 1][i][0]),
-                        __builtin_bit_cast(bf16x8, o.b[0][j][0]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = mma_bf16(__builtin_bit_cast(bf16x8, o.a[PkOps<CF>::NA - 1][i][0]),
+                                         __builtin_bit_cast(bf16x8, o.b[0][j][0]), acc[i][j]);
 #pragma unroll
             for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
                 for (int j = 0; j < CF::TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, o.a[0][i][0]),
-                        __builtin_bit_cast(bf16x8, o.b[PkOps<CF>::NA - 1][j][0]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = mma_bf16(__builtin_bit_cast(bf16x8, o.a[0][i][0]),
+                                         __builtin_bit_cast(bf16x8, o.b[PkOps<CF>::NA - 1][j][0]), acc[i][j]);
         }
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf16x8, o.a[0][i][0]), __builtin_bit_cast(bf16x8, o.b[0][j][0]),
-                    acc[i][j], 0, 0, 0);
+                acc[i][j] = mma_bf16(__builtin_bit_cast(bf16x8, o.a[0][i][0]),
+                                     __builtin_bit_cast(bf16x8, o.b[0][j][0]), acc[i][j]);
     }
 }
 
@@ -453,8 +489,8 @@ struct PackedOps {
     {
         pk_load<CF>(stage, o, g, wm0, wn0, lane);
     }
-    __device__ __forceinline__ static void compute(const Ops& o, f32x16 (&acc)[CF::TM][CF::TN], int sa8 = 0,
-                                                   int sb8 = 0)
+    __device__ __forceinline__ static void compute(const Ops& o, typename CF::Acc (&acc)[CF::TM][CF::TN],
+                                                   int sa8 = 0, int sb8 = 0)
     {
         pk_compute<CF>(o, acc, sa8, sb8);
     }
@@ -473,7 +509,7 @@ struct NoIssue {
 // last LDS reads of the stage (the caller may refill the stage from there).
 // MX: the e4m3 MFMAs take the block scales (sa8, sb8); otherwise none.
 template <class CF, class OP = PackedOps<CF>, bool MX = false, class F = NoIssue, class G = NoIssue>
-__device__ __forceinline__ void pk_mma(const char* stage, f32x16 (&acc)[CF::TM][CF::TN], int wm0,
+__device__ __forceinline__ void pk_mma(const char* stage, typename CF::Acc (&acc)[CF::TM][CF::TN], int wm0,
                                        int wn0, int lane, const F& then = F(), const G& before_last = G(),
                                        int sa8 = 0, int sb8 = 0)
 {
@@ -599,25 +635,24 @@ struct TileStore {
     const PackedArgs& a;
     int m0, n0;
     template <class SC>
-    __device__ __forceinline__ void operator()(f32x16 (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
+    __device__ __forceinline__ void operator()(typename CF::Acc (&acc)[CF::TM][CF::TN], const SC& sc, int wm0,
                                                int wn0, int lane) const
     {
         // the addresses below are computed here, not hoisted out of a loop over
         // tiles where they would hold registers through the main loop
         asm volatile("" : "+v"(lane));
-        const int h = lane >> 5, l32 = lane & 31;
         const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
         const bool read_c = (a.beta != 0.f);
 #pragma unroll
         for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
             for (int j = 0; j < CF::TN; ++j) {
-                const int r0 = m0 + wm0 + 32 * i, c0 = n0 + wn0 + 32 * j;
+                const int r0 = m0 + wm0 + CF::MS * i, c0 = n0 + wn0 + CF::MS * j;
                 const float f = a.alpha * sc(i, j);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = r0 + 8 * (r >> 2) + 4 * h + (r & 3);
-                    const int col = c0 + l32;
+                for (int r = 0; r < CF::AR; ++r) {
+                    const int row = r0 + CF::out_row(r, lane);
+                    const int col = c0 + CF::out_col(lane);
                     if (!full && (row >= a.M || col >= a.N)) continue;
                     float* p = a.C + (int64_t)row * a.ldc + col;
                     float v = f * acc[i][j][r];
@@ -655,13 +690,13 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
     bl.init(a, n0, lane, wave);
     constexpr bool scaled = SCALED && (CF::MODE == MODE_BF16 || CF::MODE == MODE_FP8);
 
-    f32x16 acc[CF::TM][CF::TN];
+    typename CF::Acc acc[CF::TM][CF::TN];
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+            for (int r = 0; r < CF::AR; ++r) acc[i][j][r] = 0.f;
 
     const int npanel = np;
     auto issue = [&](int panel, char* stage) {  // panel: index within the range
@@ -695,7 +730,8 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
 #pragma unroll
             for (int i = 0; i < SM; ++i)
 #pragma unroll
-                for (int j = 0; j < SN; ++j) dst[i][j] = block_scale(a, m0 + wm0 + 32 * i, n0 + wn0 + 32 * j, kb);
+                for (int j = 0; j < SN; ++j)
+                    dst[i][j] = block_scale(a, m0 + wm0 + CF::MS * i, n0 + wn0 + CF::MS * j, kb);
         }
     };
     // the unit of the block whose raw scales are sa_next and sc_next (mx)
@@ -743,7 +779,7 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
 #pragma unroll
                     for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                        for (int r = 0; r < CF::AR; ++r) acc[i][j][r] *= ratio;
             }
             sc_cur[0][0] = m;
             kb_cur = kb;
@@ -759,7 +795,7 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
 #pragma unroll
                     for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                        for (int r = 0; r < CF::AR; ++r) acc[i][j][r] *= ratio;
             }
         } else {
 #pragma unroll
@@ -768,7 +804,7 @@ __device__ __forceinline__ void packed_tile_range(const PackedArgs& a, int m0, i
                 for (int j = 0; j < CF::TN; ++j) {
                     const float ratio = sc_cur[i][j] / sc_next[i][j];
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[i][j][r] *= ratio;
+                    for (int r = 0; r < CF::AR; ++r) acc[i][j][r] *= ratio;
                 }
         }
 #pragma unroll

@@ -49,7 +49,7 @@ uint64_t schedule_space_hash()
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         mix(d.dtype); mix(d.BM); mix(d.BN); mix(d.BK); mix(d.WGM); mix(d.WGN); mix(d.vec);
-        mix(d.lds_bytes); mix(d.split);
+        mix(d.lds_bytes); mix(d.split); mix(d.mfma);
     }
     return h;
 }
@@ -214,8 +214,10 @@ void read_done(const char* path, uint64_t hash, std::set<std::string>* done)
 // schedule meets the same full/partial tile structure at a bounded cost.
 static int64_t gate_dim(int64_t d) { return d <= 1024 ? d : 768 + d % 256; }
 
-// Tile-order variants tried for every compiled schedule.
-static const int kOrderVariants[][2] = {{1, 0}, {4, 1}, {8, 1}, {16, 1}};
+// Tile-order variants (group_m, XCD remap) tried for every compiled schedule:
+// row-major and grouped sweeps, with and without the XCD remap.  The cost
+// model ranks the same set (costmodel.hip).
+static const int kOrderVariants[][2] = {{1, 0}, {4, 0}, {8, 0}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {32, 1}};
 
 int autotune(int64_t M, int64_t N, int64_t K, int dtype, int reps, const char* db_path)
 {

@@ -388,9 +388,9 @@ def schedule_count():
 
 
 def schedule_info(sid):
-    buf = (ctypes.c_int32 * 9)()
+    buf = (ctypes.c_int32 * 10)()
     _check(lib.tgemm_schedule_info(sid, buf), "tgemm_schedule_info")
-    keys = ("dtype", "BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "split")
+    keys = ("dtype", "BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "split", "mfma")
     return dict(zip(keys, list(buf)))
 
 
@@ -408,7 +408,8 @@ def schedule_key(sid):
     width (vec0: packed operands) and LDS bytes (which tell the pipeline depths apart)."""
     i = schedule_info(sid)
     return (f"sched:{i['dtype']}:{i['BM']}x{i['BN']}x{i['BK']}:{i['WGM']}x{i['WGN']}:"
-            f"vec{i['vec']}:lds{i['lds_bytes']}" + (":streamk" if i["split"] else ""))
+            f"vec{i['vec']}:lds{i['lds_bytes']}" + (":streamk" if i["split"] else "")
+            + (":mfma16" if i["mfma"] == 16 else ""))
 
 
 def tile_map(M, N, BM, BN, group_m, xcd_remap):
@@ -536,7 +537,7 @@ def costmodel_select(M, N, K, dtype, reps, db_path):
 
 
 def costmodel_features(M, N, K, dtype, sid, group_m, xcd):
-    out = (ctypes.c_float * 21)()
+    out = (ctypes.c_float * 22)()
     _check(lib.tgemm_costmodel_features(M, N, K, _dtype_code(dtype), sid, group_m, xcd, out),
            "tgemm_costmodel_features")
     return list(out)

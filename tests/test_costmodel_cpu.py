@@ -15,7 +15,7 @@ def tg():
 def test_features_are_finite_and_follow_the_problem(tg):
     sid = [i for i, info in tg.schedules("f32") if info["BM"] == 128 and info["vec"] == 4][0]
     f = tg.costmodel_features(4096, 2048, 1024, "f32", sid, 8, 1)
-    assert len(f) == 21 and all(math.isfinite(x) for x in f)
+    assert len(f) == 22 and all(math.isfinite(x) for x in f)
     assert f[0:3] == [12.0, 11.0, 10.0]                       # log2 M, N, K
     assert f[3:6] == [0.0, 0.0, 0.0]                          # dtype one-hot (f32)
     assert f[6:9] == [7.0, 7.0, math.log2(tg.schedule_info(sid)["BK"])]
@@ -29,6 +29,9 @@ def test_features_are_finite_and_follow_the_problem(tg):
     assert f[20] == 0.0                                       # one workgroup per tile
     sk = [i for i, info in tg.schedules("f32") if info["split"] == 1][0]
     assert tg.costmodel_features(4097, 2048, 1024, "f32", sk, 8, 1)[20] == 1.0   # stream-K
+    assert f[21] == 0.0                                       # 32 x 32 MFMA blocks
+    m16 = [i for i, info in tg.schedules("f32") if info["mfma"] == 16][0]
+    assert tg.costmodel_features(4097, 2048, 1024, "f32", m16, 8, 1)[21] == 1.0
 
 
 def test_weight_file_faults_are_refused(tg, tmp_path):

@@ -109,11 +109,16 @@ INPLACE_DIMS_ODD = [(1, 1, 1), (5, 7, 3), (65, 67, 21), (131, 129, 37), (70, 3, 
                     (33, 250, 15), (250, 33, 31), (2, 130, 1001)]
 
 
+# tile threshold NEVER: every problem on 64 x 64 in-place tiles; 0: every one on 128 x 128
+IP_TILE = {64: {"threshold": NEVER, "large": NEVER}, 128: {"threshold": 0, "large": NEVER}}
+
+
+@pytest.mark.parametrize("tile", [64, 128])
 @pytest.mark.parametrize("pad", [4, 3], ids=["vec16", "vec4"])
 @pytest.mark.parametrize("dims", [INPLACE_DIMS, INPLACE_DIMS_ODD], ids=["aligned", "odd"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad):
-    # All problems take the in-place tiles (direct 64 x 64 class).  A and B sit in buffers
+def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad, tile):
+    # All problems take the in-place tiles of one size.  A and B sit in buffers
     # `pad` (or pad + 4) columns wider than the matrices, the extra columns NaN: A past K
     # (the row's tail) must read as zero, and B's columns past N only reach accumulator
     # columns that are never stored.  C's canary columns must stay NaN.  Odd dimensions or
@@ -132,8 +137,8 @@ def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad):
         views.append(Cd)
     alphas = [1.5 if p % 2 else 1.0 for p in range(len(host))]
     betas = [0.5 if p % 3 else 0.0 for p in range(len(host))]
-    print(f"in-place {dtype} pad {pad}", flush=True)
-    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape={"threshold": NEVER, "large": NEVER})
+    print(f"in-place {tile} {dtype} pad {pad}", flush=True)
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape=IP_TILE[tile])
     torch.cuda.synchronize()
     for p, h in enumerate(host):
         ref = oracle.gemm(h[0], h[1], h[2], alphas[p], betas[p])
@@ -142,12 +147,13 @@ def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad):
         assert torch.isnan(views[p][:, h[2].shape[1]:]).all()
 
 
+@pytest.mark.parametrize("tile", [64, 128])
 @pytest.mark.parametrize("dims", [INPLACE_DIMS, INPLACE_DIMS_ODD], ids=["aligned", "odd"])
 @pytest.mark.parametrize("dtype", ["f32", "x3"])
-def test_inplace_tiles_uniform_inputs(tg, dtype, dims):
+def test_inplace_tiles_uniform_inputs(tg, dtype, dims, tile):
     host = _problem_set(dims, 5500)
     alphas, betas = [1.0] * len(host), [1.0] * len(host)
-    got = _run_batched(tg, host, alphas, betas, dtype, {"threshold": NEVER, "large": NEVER})
+    got = _run_batched(tg, host, alphas, betas, dtype, IP_TILE[tile])
     for p, (h, g) in enumerate(zip(host, got)):
         ref = oracle.gemm(h[0], h[1], h[2], 1.0, 1.0)
         assert oracle.normwise_error(g.numpy(), ref) <= 1e-5, f"problem {p} {dims[p]}"

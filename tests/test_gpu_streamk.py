@@ -45,7 +45,7 @@ def test_every_dtype_has_stream_k_forms(tg):
         for sid, info in sk:
             assert info["vec"] == 0
             twin = [s for s, i in tg.schedules(dt) if i["split"] == 0 and
-                    all(i[k] == info[k] for k in ("BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes"))]
+                    all(i[k] == info[k] for k in ("BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "mfma"))]
             assert len(twin) == 1, tg.schedule_key(sid)
 
 
