@@ -163,9 +163,10 @@ int tgemm_quantize_tiles(int64_t rows, int64_t cols, const float* X, int64_t ldx
  * assigns each problem a tile class by the set's plan shape (below), builds
  * the tile index space and uploads a descriptor table to device memory owned
  * by the library; later calls with
- * the same set launch at most three kernels (packing pass, packed-class
- * tiles, direct-class tiles; see tgemm_batched_with_shape for the two
- * classes).  The plan shape is what tgemm_batched_autotune measured for sets
+ * the same set launch at most five kernels (packing pass, packed-class
+ * tiles, in-place 128 x 128 tiles, in-place 64 x 64 tiles, direct tiles; see
+ * tgemm_batched_with_shape for the classes).  The plan shape is what
+ * tgemm_batched_autotune measured for sets
  * of these dimensions, else threshold 96 and no packed class.  A plan with packed
  * problems owns a workspace of 4 bytes per element of their A and B (rows
  * padded to 256, K to a multiple of 32) until tgemm_shutdown.
@@ -314,10 +315,13 @@ int tgemm_conv3x3_packed_shape(int dtype, int i, int* bm, int* bn, int* bk, int*
  * (>= 0; INT32_MAX: none) take the packed path: a packing pass copies their A
  * and B^T into a plan-owned workspace (K-contiguous, zero-padded; array
  * packing, Section I) and 256 x 256 macro-tiles stream K panels from it into
- * LDS.  The other problems take the direct path: 128 x 128 macro-tiles when M
- * and N both reach `threshold` (>= 0; INT32_MAX: 64 x 64 everywhere), 64 x 64
- * otherwise, loading A and B from the caller's matrices.  Plans are cached
- * per shape.  Returns TGEMM_INVALID_VALUE for a negative threshold, otherwise
+ * LDS.  The other problems take 128 x 128 macro-tiles when M and N both reach
+ * `threshold` (>= 0; INT32_MAX: 64 x 64 everywhere), 64 x 64 otherwise, with
+ * A and B read from the caller's matrices: K panels straight into LDS
+ * (in-place tiles; 16-byte loads where rows are 16-byte aligned and K and N
+ * are multiples of 4, else 4-byte loads), or, for problems whose tile rows
+ * exceed the 2^31-byte reach of a buffer offset, register-staged direct
+ * tiles.  Plans are cached per shape.  Returns TGEMM_INVALID_VALUE for a negative threshold, otherwise
  * as tgemm_batched.
  */
 int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
