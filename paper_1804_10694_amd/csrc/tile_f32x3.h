@@ -84,6 +84,36 @@ __device__ __forceinline__ void split_bf16(const float x, __bf16& hi, __bf16& lo
     lo = (__bf16)(x - (float)hi);         // x - hi is exact in float32
 }
 
+// The same split of two values at once: one packed conversion (round to
+// nearest even, as above) per pair for the high parts and one for the low
+// parts; the high parts go back to float32 by moving their bits into place.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16_pair(float x0, float x1, uint32_t& hi, uint32_t& lo)
+{
+    const bf16x2_t h = __builtin_convertvector(f32x2_t{x0, x1}, bf16x2_t);
+    hi = __builtin_bit_cast(uint32_t, h);
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x0 - h0, x1 - h1}, bf16x2_t));
+}
+
+// Eight consecutive values x[0..7] into eight high and eight low parts.
+template <class X>
+__device__ __forceinline__ void split_bf16x8(const X& x, bf16x8& hi, bf16x8& lo)
+{
+    typedef uint32_t u32v4 __attribute__((ext_vector_type(4)));
+    u32v4 h, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        uint32_t hh, ll;
+        split_bf16_pair(x[2 * e], x[2 * e + 1], hh, ll);
+        h[e] = hh;
+        l[e] = ll;
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
 template <int KU> struct UnitVec;
 template <> struct UnitVec<4> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct UnitVec<8> { typedef float type __attribute__((ext_vector_type(8))); };
@@ -219,13 +249,7 @@ struct Panel {
             *reinterpret_cast<fu*>(hi_arr + slot * 16) = x;
         } else {
             bf16x8 h, l;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                __bf16 hh, ll;
-                split_bf16(x[e], hh, ll);
-                h[e] = hh;
-                l[e] = ll;
-            }
+            split_bf16x8(x, h, l);
             *reinterpret_cast<bf16x8*>(hi_arr + slot * 16) = h;
             *reinterpret_cast<bf16x8*>(lo_arr + slot * 16) = l;
         }

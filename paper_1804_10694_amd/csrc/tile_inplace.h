@@ -258,13 +258,7 @@ struct InplaceOps<CF, MODE_X3> {
 
     __device__ __forceinline__ static void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo)
     {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            __bf16 hh, ll;
-            split_bf16(x[e], hh, ll);
-            hi[e] = hh;
-            lo[e] = ll;
-        }
+        split_bf16x8(x, hi, lo);
     }
 
     __device__ __forceinline__ static void load_a(const char* la, Ops& o, int g, int wm0, int lane)

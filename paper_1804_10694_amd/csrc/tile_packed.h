@@ -85,13 +85,8 @@ __device__ __forceinline__ void pack_row_group(const void* X, int64_t ldx, int R
             *reinterpret_cast<f32x4*>(dst + 4) = v1;
         } else {
             bf16x8 h, l;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                __bf16 hh, ll;
-                split_bf16(e < 4 ? v0[e] : v1[e - 4], hh, ll);
-                h[e] = hh;
-                l[e] = ll;
-            }
+            const float x[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+            split_bf16x8(x, h, l);
             *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(P) + o) = h;
             *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(Plo) + o) = l;
         }
@@ -196,13 +191,8 @@ __device__ __forceinline__ void pack_col_block(const void* X, int64_t ldx, int K
                         f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
             } else if (MODE == MODE_X3) {
                 bf16x8 h[2], l[2];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    __bf16 hh, ll;
-                    split_bf16(v[j], hh, ll);
-                    h[j / 8][j % 8] = hh;
-                    l[j / 8][j % 8] = ll;
-                }
+                split_bf16x8(v, h[0], l[0]);
+                split_bf16x8(v + 8, h[1], l[1]);
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(P) + o + 8 * q) = h[q];
