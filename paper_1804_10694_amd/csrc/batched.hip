@@ -256,17 +256,15 @@ __global__ void __launch_bounds__(256) small_batched_kernel(SmallArgs a)
         if constexpr (T == 16) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
         else acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
-    const bool read_c = a.beta != 0.f;
+    constexpr int AR = T == 16 ? 4 : 16;
+    write_c<1, 1, AR>(
+        C, a.ldc, a.M, a.N, a.beta, (T == 16) ? 4 * (lane / 16) : 4 * (lane / 32), lane % T,
+        [&](int, int, float (&v)[AR]) {
 #pragma unroll
-    for (int r = 0; r < (T == 16 ? 4 : 16); ++r) {
-        const int row = (T == 16) ? 4 * (lane / 16) + r : 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
-        const int col = lane % T;
-        if (row >= a.M || col >= a.N) continue;
-        float* c = C + (int64_t)row * a.ldc + col;
-        float v = a.alpha * acc[r];
-        if (read_c) v = fmaf(a.beta, *c, v);
-        *c = v;
-    }
+            for (int r = 0; r < AR; ++r) v[r] = a.alpha * acc[r];
+        },
+        [](int, int, int& r0, int& c0) { r0 = c0 = 0; },
+        [](int r) { return (T == 16) ? r : 8 * (r / 4) + (r % 4); });
 }
 
 // Persistent kernels of the in-place classes (64 x 64 and 128 x 128 tiles).

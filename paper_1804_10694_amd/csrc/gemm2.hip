@@ -142,7 +142,6 @@ __global__ void __launch_bounds__(256, (kG2Occ<MODE, N1P>)) gemm2_kernel(G2Args 
     d.K = g.N1;
     const int wn0 = wave * P2::WTN;
     const int npanel = (g.N1 + G::BK - 1) / G::BK;
-    const bool read_e = g.beta != 0.f;
     for (int n0 = 0; n0 < g.N2; n0 += G::CHUNK) {
         InplaceB<P2, VEC> dl;
         dl.init(d, n0, lane, wave);
@@ -170,20 +169,17 @@ __global__ void __launch_bounds__(256, (kG2Occ<MODE, N1P>)) gemm2_kernel(G2Args 
         }
         wait_lds_reads();
         lds_barrier();  // every wave is done with the stages before the next chunk refills them
+        write_c<P2::TM, P2::TN, 16>(
+            g.E, g.lde, g.M, g.N2, g.beta, 4 * h, l32,
+            [&](int i, int j, float (&v)[16]) {
 #pragma unroll
-        for (int i = 0; i < P2::TM; ++i)
-#pragma unroll
-            for (int j = 0; j < P2::TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                    const int col = n0 + wn0 + 32 * j + l32;
-                    if (row >= g.M || col >= g.N2) continue;
-                    float* p = g.E + (int64_t)row * g.lde + col;
-                    float v = g.alpha * acc[i][j][r];
-                    if (read_e) v = fmaf(g.beta, *p, v);
-                    *p = v;
-                }
+                for (int r = 0; r < 16; ++r) v[r] = g.alpha * acc[i][j][r];
+            },
+            [&](int i, int j, int& r0, int& c0) {
+                r0 = m0 + 32 * i;
+                c0 = n0 + wn0 + 32 * j;
+            },
+            [](int r) { return 8 * (r >> 2) + (r & 3); });
     }
 }
 

@@ -95,6 +95,10 @@ __device__ __forceinline__ int sk_owner(const SkArgs& k, int i)
     return i < big ? i / (k.q + 1) : k.r + (i - big) / k.q;
 }
 
+// Cache policy bits of a buffer load (gfx950): sc1, the device-scope policy the
+// compiler gives an agent-scope atomic load.
+constexpr int kSc1 = 16;
+
 // Epilogue of a stream-K range that covers part of tile t.
 template <class CF>
 struct SkPartial {
@@ -111,7 +115,7 @@ struct SkPartial {
 
     // Sum r of block (i, j) of this lane in a slot: the 64 lanes of a wave hold
     // 64 consecutive floats, so each (device-scope, 4-byte) store or load of a
-    // wave covers 256 contiguous bytes.
+    // wave covers 256 contiguous bytes, and sum r + 1 follows 256 bytes later.
     __device__ __forceinline__ static int elem(int wave, int i, int j, int r, int lane)
     {
         return (((wave * CF::TM + i) * CF::TN + j) * CF::AR + r) * 64 + lane;
@@ -145,38 +149,34 @@ struct SkPartial {
         }
         __syncthreads();
         if (!*flag) return;
-        // sum every range's partial (this one's included, read back) in K order,
-        // four sums at a time
-        const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
-        const bool read_c = (a.beta != 0.f);
+        // sum every range's partial (this one's included, read back) in K order
+        write_c<CF::TM, CF::TN, CF::AR>(
+            a.C, a.ldc, a.M, a.N, a.beta, CF::out_row(0, lane), CF::out_col(lane),
+            [&](int i, int j, float (&s)[CF::AR]) {
 #pragma unroll
-        for (int i = 0; i < CF::TM; ++i)
+                for (int r = 0; r < CF::AR; ++r) s[r] = 0.f;
+                for (int u = u0; u <= u1; ++u) {
+                    // the block's sums in slot u: one uniform range, the lane's
+                    // offset, and r * 256 bytes as the instruction's offset; the
+                    // loads carry the device-scope cache policy of the stores (sc1)
+                    // and go out together, one memory round trip per slot
+                    const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+                        slot(u) + elem(wave, i, j, 0, 0), 0, CF::AR * 64 * 4, 0x00020000);
+                    float x[CF::AR];
 #pragma unroll
-            for (int j = 0; j < CF::TN; ++j) {
-                const int r0 = m0 + wm0 + CF::MS * i, c0 = n0 + wn0 + CF::MS * j;
+                    for (int r = 0; r < CF::AR; ++r)
+                        x[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src, lane * 4 + r * 256, 0, kSc1));
 #pragma unroll
-                for (int q = 0; q < CF::AR / 4; ++q) {
-                    f32x4 s4 = {0.f, 0.f, 0.f, 0.f};
-                    for (int u = u0; u <= u1; ++u) {
-                        const float* src = slot(u);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            s4[e] += __hip_atomic_load(src + elem(wave, i, j, 4 * q + e, lane), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = 4 * q + e;
-                        const int row = r0 + CF::out_row(r, lane);
-                        const int col = c0 + CF::out_col(lane);
-                        if (!full && (row >= a.M || col >= a.N)) continue;
-                        float* pc = a.C + (int64_t)row * a.ldc + col;
-                        float val = a.alpha * s4[e];
-                        if (read_c) val = fmaf(a.beta, *pc, val);
-                        *pc = val;
-                    }
+                    for (int r = 0; r < CF::AR; ++r) s[r] += x[r];
                 }
-            }
+#pragma unroll
+                for (int r = 0; r < CF::AR; ++r) s[r] *= a.alpha;
+            },
+            [&](int i, int j, int& r0, int& c0) {
+                r0 = m0 + wm0 + CF::MS * i;
+                c0 = n0 + wn0 + CF::MS * j;
+            },
+            [](int r) { return CF::out_row(r, 0); });
     }
 };
 

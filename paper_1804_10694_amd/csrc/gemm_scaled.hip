@@ -19,6 +19,7 @@
 // MFMA: v_mfma_f32_32x32x16_bf16 and v_mfma_f32_32x32x64_f8f6f4 (e4m3 x e4m3).
 #include <hip/hip_runtime.h>
 
+#include "epilogue.h"
 #include "kargs.h"
 #include "registry.h"
 #include "../../include/tgemm.h"
@@ -290,21 +291,17 @@ __device__ __forceinline__ void scaled_body(const GemmArgs& a, int m0, int n0, c
     }
 
     const int h = lane >> 5, l32 = lane & 31;
-    const bool read_c = (a.beta != 0.f);
+    write_c<CF::TM, CF::TN, 16>(
+        a.C, a.ldc, a.M, a.N, a.beta, 4 * h, l32,
+        [&](int i, int j, float (&v)[16]) {
 #pragma unroll
-    for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < CF::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = n0 + wn0 + 32 * j + l32;
-                if (EDGE && (row >= a.M || col >= a.N)) continue;
-                float* p = a.C + (int64_t)row * a.ldc + col;
-                float v = a.alpha * acc[i][j][r];
-                if (read_c) v = fmaf(a.beta, *p, v);
-                *p = v;
-            }
+            for (int r = 0; r < 16; ++r) v[r] = a.alpha * acc[i][j][r];
+        },
+        [&](int i, int j, int& r0, int& c0) {
+            r0 = m0 + wm0 + 32 * i;
+            c0 = n0 + wn0 + 32 * j;
+        },
+        [](int r) { return 8 * (r >> 2) + (r & 3); });
 }
 
 template <class CF>

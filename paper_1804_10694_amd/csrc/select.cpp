@@ -110,12 +110,12 @@ bool dense_vec_ok(int64_t N, int64_t K, int dtype)
     return (K * es) % 16 == 0 && (N * es) % 16 == 0;
 }
 
-int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds, int mfma)
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds, int mfma, int split)
 {
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec &&
-            d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds) && d.split == 0 &&
+            d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds) && d.split == split &&
             d.mfma == mfma)
             return i;
     }
@@ -177,12 +177,39 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //  - f32 with 256 to 383 tiles of 128 x 256 (half to three quarters of a
     //    wave at two workgroups per CU): 128 x 128 tiles on 16 x 16 MFMA blocks,
     //    four workgroups per CU (3000^3: 0.59 ms against 0.73 for 128 x 256).
+    //  - stream-K (f32 128 x 256, x3 256 x 256) where whole tiles would leave
+    //    a large part of the last wave of workgroups idle: f32 when the tiles
+    //    fill less than 85% of their waves (4097 x 3001 x 2053: 0.48 ms against
+    //    0.57; 3000^3 0.48 against 0.58; 2500 x 1800 x 4000 0.36 against 0.50;
+    //    8192^3 and 3500 x 2100 x 1500, at 100% and 93%, keep whole tiles), and
+    //    f32 and x3 when too few tiles remain for the packed whole-tile forms
+    //    (x3 1024 x 1024 x 8192: 0.14 ms against 0.19); in both cases only with
+    //    at least 8 K panels per workgroup of the stream-K wave and enough
+    //    tiles (16 and 8) that few workgroups share one.
     if (K >= 512 && packed_k_ok(K, dtype)) {
         int id = -1;
+        const int64_t panels16 = (K + 15) / 16, panels32 = (K + 31) / 32;
+        // fraction of the launched waves the tiles fill, at `slots` resident workgroups
+        auto fill = [&](int64_t t, int64_t slots) { return (double)t / (double)(((t + slots - 1) / slots) * slots); };
         if (dtype == TGEMM_F32) {
-            if (tiles(128, 256) >= 384) id = find_schedule(dtype, 128, 256, 16, 0, 4, 2);
-            else if (tiles(128, 256) >= 256) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 32768, 16);
-            else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
+            double f = 0.0;  // 128 x 256: two workgroups per CU; the 128 x 128 forms four and two
+            if (tiles(128, 256) >= 384) {
+                id = find_schedule(dtype, 128, 256, 16, 0, 4, 2);
+                f = fill(tiles(128, 256), 512);
+            } else if (tiles(128, 256) >= 256) {
+                id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 32768, 16);
+                f = fill(tiles(128, 128), 1024);
+            } else if (tiles(128, 128) >= 192) {
+                id = find_schedule(dtype, 128, 128, 16, 0, 2, 2, 65536);
+                f = fill(tiles(128, 128), 512);
+            }
+            if (f < 0.85 && tiles(128, 256) >= 16 && tiles(128, 256) * panels16 >= 8 * 512) {
+                const int sk = find_schedule(dtype, 128, 256, 16, 0, 4, 2, -1, 32, 1);
+                if (sk >= 0) id = sk;
+            }
+        } else if (dtype == TGEMM_F32_BF16X3 && tiles(256, 256) < 128 && tiles(128, 128) < 192) {
+            if (tiles(256, 256) >= 8 && tiles(256, 256) * panels32 >= 8 * 256)
+                id = find_schedule(dtype, 256, 256, 32, 0, 2, 4, -1, 32, 1);
         } else if (dtype == TGEMM_FP8_E4M3) {
             if (tiles(256, 256) >= 128) id = find_schedule(dtype, 256, 256, 128, 0, 4, 2);
             else if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, 0, 2, 2, 32768);

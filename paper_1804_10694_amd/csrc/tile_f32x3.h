@@ -26,6 +26,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "epilogue.h"
 #include "kargs.h"
 
 namespace tg {
@@ -367,21 +368,17 @@ __device__ __forceinline__ void tile_body(const GemmArgs& a, int m0, int n0, cha
     // 32x32 accumulator layout: register r of lane l holds
     // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the block.
     const int h = lane >> 5, l32 = lane & 31;
-    const bool read_c = (a.beta != 0.f);
+    write_c<CF::TM, CF::TN, 16>(
+        a.C, a.ldc, a.M, a.N, a.beta, 4 * h, l32,
+        [&](int i, int j, float (&v)[16]) {
 #pragma unroll
-    for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < CF::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = n0 + wn0 + 32 * j + l32;
-                if (EDGE && (row >= a.M || col >= a.N)) continue;
-                float* p = a.C + (int64_t)row * a.ldc + col;
-                float v = a.alpha * acc[i][j][r];
-                if (read_c) v = fmaf(a.beta, *p, v);
-                *p = v;
-            }
+            for (int r = 0; r < 16; ++r) v[r] = a.alpha * acc[i][j][r];
+        },
+        [&](int i, int j, int& r0, int& c0) {
+            r0 = m0 + wm0 + 32 * i;
+            c0 = n0 + wn0 + 32 * j;
+        },
+        [](int r) { return 8 * (r >> 2) + (r & 3); });
 }
 
 }  // namespace tg

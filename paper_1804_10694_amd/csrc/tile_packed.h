@@ -631,25 +631,18 @@ struct TileStore {
         // the addresses below are computed here, not hoisted out of a loop over
         // tiles where they would hold registers through the main loop
         asm volatile("" : "+v"(lane));
-        const bool full = (m0 + CF::BM <= a.M) && (n0 + CF::BN <= a.N);
-        const bool read_c = (a.beta != 0.f);
-#pragma unroll
-        for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-            for (int j = 0; j < CF::TN; ++j) {
-                const int r0 = m0 + wm0 + CF::MS * i, c0 = n0 + wn0 + CF::MS * j;
+        write_c<CF::TM, CF::TN, CF::AR>(
+            a.C, a.ldc, a.M, a.N, a.beta, CF::out_row(0, lane), CF::out_col(lane),
+            [&](int i, int j, float (&v)[CF::AR]) {
                 const float f = a.alpha * sc(i, j);
 #pragma unroll
-                for (int r = 0; r < CF::AR; ++r) {
-                    const int row = r0 + CF::out_row(r, lane);
-                    const int col = c0 + CF::out_col(lane);
-                    if (!full && (row >= a.M || col >= a.N)) continue;
-                    float* p = a.C + (int64_t)row * a.ldc + col;
-                    float v = f * acc[i][j][r];
-                    if (read_c) v = fmaf(a.beta, *p, v);
-                    *p = v;
-                }
-            }
+                for (int r = 0; r < CF::AR; ++r) v[r] = f * acc[i][j][r];
+            },
+            [&](int i, int j, int& r0, int& c0) {
+                r0 = m0 + wm0 + CF::MS * i;
+                c0 = n0 + wn0 + CF::MS * j;
+            },
+            [](int r) { return CF::out_row(r, 0); });
     }
 };
 

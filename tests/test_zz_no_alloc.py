@@ -1,7 +1,10 @@
 """tgemm_noalloc (the entry point for callers that cannot allocate) against tgemm.
 
 Both pick the same schedule (the default policy), so their results must agree
-bit for bit; both are also held to the oracle's bar.  Two calls in a row, the
+bit for bit, except where that schedule is a stream-K form: it needs counters
+the library allocates, so tgemm_noalloc runs the same tiles one workgroup per
+tile instead, which must then agree bit for bit with that whole-tile schedule.
+Both are also held to the oracle's bar.  Two calls in a row, the
 second with a smaller problem, check that the shared static workspace keeps no
 state a later call depends on; a problem whose packing workspace exceeds the
 static array is refused before any launch.
@@ -29,6 +32,18 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _whole_tile_form(tg, dt, sid):
+    """The schedule tgemm_noalloc runs for choice `sid`: itself, or the
+    whole-tile schedule of a stream-K form."""
+    info = tg.schedule_info(sid)
+    if info["split"] == 0:
+        return sid
+    keys = ("BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "mfma")
+    twin = [s for s, i in tg.schedules(dt) if i["split"] == 0 and all(i[k] == info[k] for k in keys)]
+    assert len(twin) == 1
+    return twin[0]
+
+
 def _call(tg, fn, A, B, C, alpha, beta, dt):
     M, K = A.shape
     N = B.shape[1]
@@ -46,17 +61,22 @@ SIZES = [((2048, 2048, 1024), (2000, 1600, 600)), ((3000, 2500, 1100), (1700, 19
 def test_noalloc_matches_tgemm_two_calls(tg, dt, sizes):
     for n, (M, N, K) in enumerate(sizes):
         print(f"noalloc {dt} call {n}: {M}x{N}x{K}", flush=True)
-        sid, _, _ = tg.select_schedule(M, N, K, dt)
+        sid, gm, xcd = tg.select_schedule(M, N, K, dt)
         assert tg.schedule_info(sid)["vec"] == 0, "the case must take a packed schedule"
         A, B, C0 = inputs.gemm_inputs(M, N, K, seed=900 + n)
         Ad, Bd = A.to(DEV), B.to(DEV)
-        Cn, Ct = C0.to(DEV), C0.to(DEV)
+        Cn, Ct, Cw = C0.to(DEV), C0.to(DEV), C0.to(DEV)
         assert _call(tg, tg.lib.tgemm_noalloc, Ad, Bd, Cn, 1.0, 0.5, dt) == 0
         assert _call(tg, tg.lib.tgemm, Ad, Bd, Ct, 1.0, 0.5, dt) == 0
+        tg.gemm_with_schedule(Ad, Bd, Cw, 1.0, 0.5, dt, _whole_tile_form(tg, dt, sid), gm, xcd)
         torch.cuda.synchronize()
-        assert torch.equal(Cn, Ct)
-        err = oracle.normwise_error(Cn.cpu().numpy(), oracle.gemm(A, B, C0, 1.0, 0.5))
-        assert err <= 1e-5, err
+        assert torch.equal(Cn, Cw)
+        if tg.schedule_info(sid)["split"] == 0:
+            assert torch.equal(Cn, Ct)
+        ref = oracle.gemm(A, B, C0, 1.0, 0.5)
+        for out in (Cn, Ct):
+            err = oracle.normwise_error(out.cpu().numpy(), ref)
+            assert err <= 1e-5, err
 
 
 @pytest.mark.parametrize("dt", ["fp8", "bf16"])
