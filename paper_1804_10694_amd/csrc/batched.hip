@@ -150,15 +150,38 @@ __device__ __forceinline__ void scale_tile(const GroupDesc& g, int local)
     }
 }
 
+// Work list of a persistent launch split into one run per XCD: the workgroups
+// of XCD x (ids b with b % 8 == x, the hardware's round-robin placement) take
+// positions start[x] .. start[x + 1] - 1 of the list, striding over them, so
+// the tiles an XCD runs together are neighbours in the list (tiles of one
+// problem in the tiling map's grouped order) and share that XCD's L2.  The
+// launch has at least 8 workgroups.
+struct XcdRuns {
+    int start[kNumXcd + 1];
+};
+
+// This workgroup's first position, the end of its XCD's run, and its stride.
+struct XcdWalk {
+    int first, end, stride;
+    __device__ __forceinline__ explicit XcdWalk(const XcdRuns& runs)
+    {
+        const int x = (int)blockIdx.x % kNumXcd;
+        first = runs.start[x] + (int)blockIdx.x / kNumXcd;
+        end = runs.start[x + 1];
+        stride = ((int)gridDim.x - x + kNumXcd - 1) / kNumXcd;
+    }
+};
+
 // Packing pass over every packed problem in one launch: work unit u is unit
 // map[u].y of problem map[u].x; a problem's units are its A row units (256
 // groups of 8 k each) and then its 64 x 64 B^T blocks.
 template <int MODE>
 __global__ void __launch_bounds__(256) grouped_pack_kernel(const GroupDesc* __restrict__ desc,
-                                                           const int2* __restrict__ map, int total)
+                                                           const int2* __restrict__ map, XcdRuns runs)
 {
     __shared__ float tile[64][65];
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    const XcdWalk w(runs);
+    for (int u = w.first; u < w.end; u += w.stride) {
         const int2 pl = map[u];
         const GroupDesc& g = desc[pl.x];
         const int local = pl.y;
@@ -180,11 +203,12 @@ __global__ void __launch_bounds__(256) grouped_pack_kernel(const GroupDesc* __re
 // Persistent kernel of the packed class.
 template <int MODE>
 __global__ void __launch_bounds__(GroupPacked<MODE>::NT, 1)
-    grouped_packed_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, int total)
+    grouped_packed_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, XcdRuns runs)
 {
     using CF = GroupPacked<MODE>;
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const XcdWalk w(runs);
+    for (int t = w.first; t < w.end; t += w.stride) {
         const int2 pl = map[t];  // (problem, tile within it)
         const GroupDesc& g = desc[pl.x];
         PackedArgs a;
@@ -272,11 +296,12 @@ template <int MODE, int T>
 using InplaceCfgOf = typename std::conditional<T == 64, GroupInplace<MODE>, GroupInplace128<MODE>>::type;
 template <int MODE, int T>
 __global__ void __launch_bounds__((InplaceCfgOf<MODE, T>::NT), (T == 64 ? kInplaceOcc<MODE> : kInplace128Occ<MODE>))
-    grouped_inplace_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, int total)
+    grouped_inplace_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, XcdRuns runs)
 {
     using CF = InplaceCfgOf<MODE, T>;
     __shared__ __attribute__((aligned(1024))) char lds[CF::LDS_BYTES];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const XcdWalk w(runs);
+    for (int t = w.first; t < w.end; t += w.stride) {
         const int2 pl = map[t];  // (problem, tile within it)
         const GroupDesc& g = desc[pl.x];
         PackedArgs a;
@@ -315,11 +340,12 @@ __global__ void __launch_bounds__((InplaceCfgOf<MODE, T>::NT), (T == 64 ? kInpla
 // per CU to hide the short tiles' load and store latency.
 template <int MODE, bool MIXED>
 __global__ void __launch_bounds__(256, MIXED ? GroupCfgs<MODE>::OCC_MIXED : GroupCfgs<MODE>::OCC_SMALL)
-    grouped_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, int total)
+    grouped_kernel(const GroupDesc* __restrict__ desc, const int2* __restrict__ map, XcdRuns runs)
 {
     using G = GroupCfgs<MODE>;
     __shared__ __attribute__((aligned(16))) char lds[MIXED ? G::LDS : G::C0::LDS_BYTES];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const XcdWalk w(runs);
+    for (int t = w.first; t < w.end; t += w.stride) {
         const int2 pl = map[t];  // (problem, tile within it)
         const GroupDesc& g = desc[pl.x];
         const int local = pl.y;
@@ -365,6 +391,7 @@ struct Space {
     int2* d_map = nullptr;  // tile (or packing unit) -> (problem, index within it)
     int total = 0;
     int grid = 0;
+    XcdRuns runs = {};
 };
 
 struct Plan {
@@ -432,24 +459,6 @@ std::map<uint64_t, Shape> g_tuned_shape;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Tiles (or units) numbered consecutively over `owners` -> (owner, index within it).
-int upload_map(const std::vector<int>& counts, const std::vector<int>& owners, Space* sp)
-{
-    int64_t total = 0;
-    for (int c : counts) total += c;
-    if (total > INT32_MAX) return TGEMM_NOT_SUPPORTED;
-    sp->total = (int)total;
-    if (total == 0) return TGEMM_SUCCESS;
-    std::vector<int2> map;
-    map.reserve((size_t)total);
-    for (size_t i = 0; i < counts.size(); ++i)
-        for (int t = 0; t < counts[i]; ++t) map.push_back(make_int2(owners[i], t));
-    if (hipMalloc(&sp->d_map, map.size() * sizeof(int2)) != hipSuccess) return TGEMM_ALLOC_FAILED;
-    if (hipMemcpy(sp->d_map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
-        return TGEMM_LAUNCH_FAILED;
-    return TGEMM_SUCCESS;
-}
-
 int resident_grid(const void* fn, int threads, int total)
 {
     int dev = 0, cus = 256, per_cu = 1;
@@ -459,6 +468,67 @@ int resident_grid(const void* fn, int threads, int total)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return std::min(total, cus * per_cu);
+}
+
+// Work list of a persistent launch of `fn` on one resident wave: the items
+// (tiles or packing units) of owner i are (owners[i], 0 .. counts[i] - 1), each
+// of estimated cost cost[i].  The list is split into one run per XCD of about
+// equal cost: owners worth more than a quarter of an XCD's share are cut into
+// chunks of consecutive items, and owners and chunks go, dearest first, to the
+// XCD with the least cost so far; each run then lists its dearest items first.
+int upload_map(const std::vector<int>& counts, const std::vector<int>& owners, const std::vector<double>& cost,
+               const void* fn, int threads, Space* sp)
+{
+    int64_t total = 0;
+    double sum = 0.0;
+    for (size_t i = 0; i < counts.size(); ++i) {
+        total += counts[i];
+        sum += counts[i] * cost[i];
+    }
+    if (total > INT32_MAX) return TGEMM_NOT_SUPPORTED;
+    sp->total = (int)total;
+    sp->runs = XcdRuns{};
+    if (total == 0) return TGEMM_SUCCESS;
+    // every workgroup of the resident wave, so each XCD holds its share of them
+    sp->grid = std::max(resident_grid(fn, threads, INT32_MAX), kNumXcd);
+
+    struct Chunk {
+        int owner, first, count;
+        double each;
+    };
+    std::vector<Chunk> chunks;
+    const double quarter = sum / kNumXcd / 4.0;
+    for (size_t i = 0; i < counts.size(); ++i) {
+        if (counts[i] == 0) continue;
+        const int per = cost[i] > 0.0 ? (int)std::max(1.0, std::min((double)counts[i], quarter / cost[i])) : counts[i];
+        for (int f = 0; f < counts[i]; f += per)
+            chunks.push_back({(int)i, f, std::min(per, counts[i] - f), cost[i]});
+    }
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const Chunk& a, const Chunk& b) { return a.count * a.each > b.count * b.each; });
+    std::vector<std::vector<Chunk>> run(kNumXcd);
+    double load[kNumXcd] = {};
+    for (const Chunk& c : chunks) {
+        const int x = (int)(std::min_element(load, load + kNumXcd) - load);
+        load[x] += c.count * c.each;
+        run[x].push_back(c);
+    }
+    std::vector<int2> map;
+    map.reserve((size_t)total);
+    for (int x = 0; x < kNumXcd; ++x) {
+        std::stable_sort(run[x].begin(), run[x].end(), [](const Chunk& a, const Chunk& b) {
+            if (a.each != b.each) return a.each > b.each;
+            return a.owner != b.owner ? a.owner < b.owner : a.first < b.first;
+        });
+        sp->runs.start[x] = (int)map.size();
+        for (const Chunk& c : run[x])
+            for (int t = c.first; t < c.first + c.count; ++t) map.push_back(make_int2(owners[c.owner], t));
+    }
+    sp->runs.start[kNumXcd] = (int)map.size();
+    if (hipMalloc(&sp->d_map, map.size() * sizeof(int2)) != hipSuccess) return TGEMM_ALLOC_FAILED;
+    if (hipMemcpy(sp->d_map, map.data(), map.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return TGEMM_LAUNCH_FAILED;
+    return TGEMM_SUCCESS;
 }
 
 int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
@@ -543,22 +613,30 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
     std::vector<int64_t> offs(descs.size(), 0);
     std::vector<int> pack_units, packed_tiles, inplace128_tiles, inplace_tiles, direct_tiles;
     std::vector<int> pack_owner, packed_owner, inplace128_owner, inplace_owner, direct_owner;
+    // estimated cost of one tile: its area times K plus a fixed part for the
+    // pipeline fill and the epilogue (worth 32 K steps); packing units cost 1
+    std::vector<double> pack_cost, packed_cost, inplace128_cost, inplace_cost, direct_cost;
+    auto tile_cost = [](int t, int K) { return (double)t * t * (K + 32); };
     for (size_t i = 0; i < descs.size(); ++i) {
         GroupDesc& g = descs[i];
         const int tiles = g.tiles_m * g.tiles_n;
+        const int k = g.scale_only ? 0 : g.K;
         if (cls[i] == kInplace) {
             inplace_tiles.push_back(tiles);
             inplace_owner.push_back((int)i);
+            inplace_cost.push_back(tile_cost(kInplaceTile, k));
             continue;
         }
         if (cls[i] == kInplace128) {
             inplace128_tiles.push_back(tiles);
             inplace128_owner.push_back((int)i);
+            inplace128_cost.push_back(tile_cost(kInplace128Tile, k));
             continue;
         }
         if (cls[i] == kDirect) {
             direct_tiles.push_back(tiles);
             direct_owner.push_back((int)i);
+            direct_cost.push_back(tile_cost(g.scale_only ? 64 : kGroupTile[g.cfg], k));
             continue;
         }
         g.Mp = (int)round_up(g.M, kPackedTile);
@@ -572,8 +650,10 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         if (units > INT32_MAX) return TGEMM_NOT_SUPPORTED;
         pack_units.push_back((int)units);
         pack_owner.push_back((int)i);
+        pack_cost.push_back(1.0);
         packed_tiles.push_back(tiles);
         packed_owner.push_back((int)i);
+        packed_cost.push_back(tile_cost(kPackedTile, g.Kp));
         offs[i] = off;
         off += round_up((int64_t)(g.Mp + g.Np) * g.Kp * 4, 256);
     }
@@ -590,30 +670,33 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
             g.Blo = arrays == 2 ? g.Bp + b_bytes : nullptr;
         }
     }
-    int rc;
-    if ((rc = upload_map(pack_units, pack_owner, &plan->pack)) != TGEMM_SUCCESS) return rc;
-    if ((rc = upload_map(packed_tiles, packed_owner, &plan->packed)) != TGEMM_SUCCESS) return rc;
-    if ((rc = upload_map(inplace128_tiles, inplace128_owner, &plan->inplace128)) != TGEMM_SUCCESS) return rc;
-    if ((rc = upload_map(inplace_tiles, inplace_owner, &plan->inplace)) != TGEMM_SUCCESS) return rc;
-    if ((rc = upload_map(direct_tiles, direct_owner, &plan->direct)) != TGEMM_SUCCESS) return rc;
     const bool f32 = dtype == TGEMM_F32;
-    plan->pack.grid = resident_grid(f32 ? (const void*)&grouped_pack_kernel<MODE_F32>
-                                        : (const void*)&grouped_pack_kernel<MODE_X3>, 256, plan->pack.total);
-    plan->packed.grid = resident_grid(f32 ? (const void*)&grouped_packed_kernel<MODE_F32>
-                                          : (const void*)&grouped_packed_kernel<MODE_X3>,
-                                      GroupPacked<MODE_F32>::NT, plan->packed.total);
-    plan->inplace128.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 128>
-                                              : (const void*)&grouped_inplace_kernel<MODE_X3, 128>,
-                                          GroupInplace128<MODE_F32>::NT, plan->inplace128.total);
-    plan->inplace.grid = resident_grid(f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 64>
-                                           : (const void*)&grouped_inplace_kernel<MODE_X3, 64>,
-                                       GroupInplace<MODE_F32>::NT, plan->inplace.total);
     for (size_t i = 0; i < descs.size(); ++i)
         plan->mixed = plan->mixed || (cls[i] == kDirect && !descs[i].scale_only && descs[i].cfg >= 2);
     const void* direct_fn =
         plan->mixed ? (f32 ? (const void*)&grouped_kernel<MODE_F32, true> : (const void*)&grouped_kernel<MODE_X3, true>)
                     : (f32 ? (const void*)&grouped_kernel<MODE_F32, false> : (const void*)&grouped_kernel<MODE_X3, false>);
-    plan->direct.grid = resident_grid(direct_fn, 256, plan->direct.total);
+    int rc;
+    if ((rc = upload_map(pack_units, pack_owner, pack_cost,
+                         f32 ? (const void*)&grouped_pack_kernel<MODE_F32> : (const void*)&grouped_pack_kernel<MODE_X3>,
+                         256, &plan->pack)) != TGEMM_SUCCESS)
+        return rc;
+    if ((rc = upload_map(packed_tiles, packed_owner, packed_cost,
+                         f32 ? (const void*)&grouped_packed_kernel<MODE_F32>
+                             : (const void*)&grouped_packed_kernel<MODE_X3>,
+                         GroupPacked<MODE_F32>::NT, &plan->packed)) != TGEMM_SUCCESS)
+        return rc;
+    if ((rc = upload_map(inplace128_tiles, inplace128_owner, inplace128_cost,
+                         f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 128>
+                             : (const void*)&grouped_inplace_kernel<MODE_X3, 128>,
+                         GroupInplace128<MODE_F32>::NT, &plan->inplace128)) != TGEMM_SUCCESS)
+        return rc;
+    if ((rc = upload_map(inplace_tiles, inplace_owner, inplace_cost,
+                         f32 ? (const void*)&grouped_inplace_kernel<MODE_F32, 64>
+                             : (const void*)&grouped_inplace_kernel<MODE_X3, 64>,
+                         GroupInplace<MODE_F32>::NT, &plan->inplace)) != TGEMM_SUCCESS)
+        return rc;
+    if ((rc = upload_map(direct_tiles, direct_owner, direct_cost, direct_fn, 256, &plan->direct)) != TGEMM_SUCCESS) return rc;
 
     if (hipMalloc(&plan->d_desc, descs.size() * sizeof(GroupDesc)) != hipSuccess) return TGEMM_ALLOC_FAILED;
     if (hipMemcpy(plan->d_desc, descs.data(), descs.size() * sizeof(GroupDesc), hipMemcpyHostToDevice) !=
@@ -639,22 +722,22 @@ void launch_modes(const Plan& p, hipStream_t s)
 {
     if (p.pack.total > 0)
         hipLaunchKernelGGL(grouped_pack_kernel<MODE>, dim3(p.pack.grid), dim3(256), 0, s, p.d_desc,
-                           p.pack.d_map, p.pack.total);
+                           p.pack.d_map, p.pack.runs);
     if (p.packed.total > 0)
         hipLaunchKernelGGL(grouped_packed_kernel<MODE>, dim3(p.packed.grid), dim3(GroupPacked<MODE>::NT), 0,
-                           s, p.d_desc, p.packed.d_map, p.packed.total);
+                           s, p.d_desc, p.packed.d_map, p.packed.runs);
     if (p.inplace128.total > 0)
         hipLaunchKernelGGL((grouped_inplace_kernel<MODE, 128>), dim3(p.inplace128.grid),
-                           dim3(GroupInplace128<MODE>::NT), 0, s, p.d_desc, p.inplace128.d_map, p.inplace128.total);
+                           dim3(GroupInplace128<MODE>::NT), 0, s, p.d_desc, p.inplace128.d_map, p.inplace128.runs);
     if (p.inplace.total > 0)
         hipLaunchKernelGGL((grouped_inplace_kernel<MODE, 64>), dim3(p.inplace.grid), dim3(GroupInplace<MODE>::NT),
-                           0, s, p.d_desc, p.inplace.d_map, p.inplace.total);
+                           0, s, p.d_desc, p.inplace.d_map, p.inplace.runs);
     if (p.direct.total > 0 && p.mixed)
         hipLaunchKernelGGL((grouped_kernel<MODE, true>), dim3(p.direct.grid), dim3(256), 0, s, p.d_desc,
-                           p.direct.d_map, p.direct.total);
+                           p.direct.d_map, p.direct.runs);
     else if (p.direct.total > 0)
         hipLaunchKernelGGL((grouped_kernel<MODE, false>), dim3(p.direct.grid), dim3(256), 0, s, p.d_desc,
-                           p.direct.d_map, p.direct.total);
+                           p.direct.d_map, p.direct.runs);
 }
 
 int launch_plan(const Plan& p, hipStream_t s)

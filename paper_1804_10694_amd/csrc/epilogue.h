@@ -13,7 +13,8 @@ namespace tg {
 // lane of a wave); value r of a lane sits at row r0 + lane_row + rrow(r),
 // column c0 + lane_col.
 //
-// The blocks go in chunks of up to 16 values per lane.  With beta != 0 every
+// The blocks go in chunks of up to CH values per lane (16 unless the caller
+// has registers to spare).  With beta != 0 every
 // read of C in a chunk is issued before the first one is used, so a chunk
 // costs one memory round trip (a read under a branch of its own would cost one
 // per element).  Each row of a block is a buffer range that ends at C's last
@@ -22,11 +23,11 @@ namespace tg {
 // elements outside M x N read as zero and are never written, without a branch.
 // Offsets are 32-bit: with ldc >= 2^25 a plain per-element loop runs instead.
 // beta == 0 never reads C.
-template <int TM, int TN, int AR, class Val, class Org, class RowOf>
+template <int TM, int TN, int AR, int CH = 16, class Val, class Org, class RowOf>
 __device__ __forceinline__ void write_c(float* C, int64_t ldc, int M, int N, float beta, int lane_row,
                                         int lane_col, const Val& val, const Org& origin, const RowOf& rrow)
 {
-    constexpr int NB = AR >= 16 ? 1 : 16 / AR;  // blocks per chunk
+    constexpr int NB = AR >= CH ? 1 : CH / AR;  // blocks per chunk
     constexpr int NBLK = TM * TN;
     if (ldc >= (int64_t(1) << 25)) {
 #pragma unroll

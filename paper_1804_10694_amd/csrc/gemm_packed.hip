@@ -149,34 +149,50 @@ struct SkPartial {
         }
         __syncthreads();
         if (!*flag) return;
-        // sum every range's partial (this one's included, read back) in K order
-        write_c<CF::TM, CF::TN, CF::AR>(
-            a.C, a.ldc, a.M, a.N, a.beta, CF::out_row(0, lane), CF::out_col(lane),
-            [&](int i, int j, float (&s)[CF::AR]) {
+        // sum every range's partial (this one's included, read back) in K order,
+        // FB blocks at a time: for each slot, the loads of all FB blocks go out
+        // together (one uniform range per block, the lane's offset, r * 256
+        // bytes as the instruction's offset), with the device-scope cache
+        // policy of the stores (sc1); then the FB blocks are written to C
+        constexpr int NBLK = CF::TM * CF::TN;
+        constexpr int FB = (NBLK * CF::AR >= 128 ? 32 : 16) / CF::AR;
+        static_assert(FB >= 1 && NBLK % FB == 0, "fix-up chunks cover the wave tile");
 #pragma unroll
-                for (int r = 0; r < CF::AR; ++r) s[r] = 0.f;
-                for (int u = u0; u <= u1; ++u) {
-                    // the block's sums in slot u: one uniform range, the lane's
-                    // offset, and r * 256 bytes as the instruction's offset; the
-                    // loads carry the device-scope cache policy of the stores (sc1)
-                    // and go out together, one memory round trip per slot
-                    const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
-                        slot(u) + elem(wave, i, j, 0, 0), 0, CF::AR * 64 * 4, 0x00020000);
-                    float x[CF::AR];
+        for (int b0 = 0; b0 < NBLK; b0 += FB) {
+            float s[FB][CF::AR];
+#pragma unroll
+            for (int q = 0; q < FB; ++q)
+#pragma unroll
+                for (int r = 0; r < CF::AR; ++r) s[q][r] = 0.f;
+            for (int u = u0; u <= u1; ++u) {
+                const float* src = slot(u);
+                float x[FB][CF::AR];
+#pragma unroll
+                for (int q = 0; q < FB; ++q) {
+                    const int i = (b0 + q) / CF::TN, j = (b0 + q) % CF::TN;
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        const_cast<float*>(src) + elem(wave, i, j, 0, 0), 0, CF::AR * 64 * 4, 0x00020000);
 #pragma unroll
                     for (int r = 0; r < CF::AR; ++r)
-                        x[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(src, lane * 4 + r * 256, 0, kSc1));
-#pragma unroll
-                    for (int r = 0; r < CF::AR; ++r) s[r] += x[r];
+                        x[q][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4 + r * 256, 0, kSc1));
                 }
 #pragma unroll
-                for (int r = 0; r < CF::AR; ++r) s[r] *= a.alpha;
-            },
-            [&](int i, int j, int& r0, int& c0) {
-                r0 = m0 + wm0 + CF::MS * i;
-                c0 = n0 + wn0 + CF::MS * j;
-            },
-            [](int r) { return CF::out_row(r, 0); });
+                for (int q = 0; q < FB; ++q)
+#pragma unroll
+                    for (int r = 0; r < CF::AR; ++r) s[q][r] += x[q][r];
+            }
+            write_c<1, FB, CF::AR>(
+                a.C, a.ldc, a.M, a.N, a.beta, CF::out_row(0, lane), CF::out_col(lane),
+                [&](int, int q, float (&v)[CF::AR]) {
+#pragma unroll
+                    for (int r = 0; r < CF::AR; ++r) v[r] = a.alpha * s[q][r];
+                },
+                [&](int, int q, int& r0, int& c0) {
+                    r0 = m0 + wm0 + CF::MS * ((b0 + q) / CF::TN);
+                    c0 = n0 + wn0 + CF::MS * ((b0 + q) % CF::TN);
+                },
+                [](int r) { return CF::out_row(r, 0); });
+        }
     }
 };
 
