@@ -131,10 +131,11 @@ int direct_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed
     // Measured on MI355X at 8192^3: 128x128 macro-tiles beat 256-wide ones for the
     // direct kernels; 64-wide tiles keep small problems spread over the 256 CUs.
     if (dtype == TGEMM_F32) {
-        if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 32, vec);
+        // rows that 16-byte loads cannot take: 64 x 64 tiles at any size
+        if (tiles(128, 128) >= 192 && vec == 4) id = find_schedule(dtype, 128, 128, 32, vec);
         else id = find_schedule(dtype, 64, 64, 16, vec);
     } else if (dtype == TGEMM_F32_BF16X3) {
-        if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 32, vec);
+        if (tiles(128, 128) >= 192 && vec == 4) id = find_schedule(dtype, 128, 128, 32, vec);
         else id = find_schedule(dtype, 64, 64, 32, vec);
     } else if (dtype == TGEMM_BF16) {
         if (tiles(128, 128) >= 192) id = find_schedule(dtype, 128, 128, 64, vec);
@@ -177,7 +178,14 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //  - f32 with 256 to 383 tiles of 128 x 256 (half to three quarters of a
     //    wave at two workgroups per CU): 128 x 128 tiles on 16 x 16 MFMA blocks,
     //    four workgroups per CU (3000^3: 0.59 ms against 0.73 for 128 x 256).
-    //  - stream-K (f32 128 x 256, x3 256 x 256) where whole tiles would leave
+    //  - f32 and x3 with M or N at most 128 keep the direct tiles (over 2080
+    //    shapes log-uniform in [64, 8192], tuned exhaustively on MI355X, the
+    //    packed f32 128 x 256 tiles reached 0.33-0.58 of the best schedule
+    //    there), and so do rows that 16-byte loads cannot take, on 64 x 64
+    //    tiles (rule against the exhaustive optimum on that set, geometric
+    //    mean: f32 0.923 -> 0.950, x3 0.915 -> 0.926);
+    //  - stream-K (f32 128 x 256, or 128 x 128 below 384 tiles of 128 x 256;
+    //    x3 256 x 256) where whole tiles would leave
     //    a large part of the last wave of workgroups idle: f32 when the tiles
     //    fill less than 85% of their waves (4097 x 3001 x 2053: 0.48 ms against
     //    0.57; 3000^3 0.48 against 0.58; 2500 x 1800 x 4000 0.36 against 0.50;
@@ -186,7 +194,8 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    (x3 1024 x 1024 x 8192: 0.14 ms against 0.19); in both cases only with
     //    at least 8 K panels per workgroup of the stream-K wave and enough
     //    tiles (16 and 8) that few workgroups share one.
-    if (K >= 512 && packed_k_ok(K, dtype)) {
+    const bool narrow = (dtype == TGEMM_F32 || dtype == TGEMM_F32_BF16X3) && (M <= 128 || N <= 128);
+    if (K >= 512 && packed_k_ok(K, dtype) && !narrow) {
         int id = -1;
         const int64_t panels16 = (K + 15) / 16, panels32 = (K + 31) / 32;
         // fraction of the launched waves the tiles fill, at `slots` resident workgroups
@@ -204,7 +213,8 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
                 f = fill(tiles(128, 128), 512);
             }
             if (f < 0.85 && tiles(128, 256) >= 16 && tiles(128, 256) * panels16 >= 8 * 512) {
-                const int sk = find_schedule(dtype, 128, 256, 16, 0, 4, 2, -1, 32, 1);
+                const int sk = tiles(128, 256) >= 384 ? find_schedule(dtype, 128, 256, 16, 0, 4, 2, -1, 32, 1)
+                                                      : find_schedule(dtype, 128, 128, 16, 0, 2, 2, -1, 32, 1);
                 if (sk >= 0) id = sk;
             }
         } else if (dtype == TGEMM_F32_BF16X3 && tiles(256, 256) < 128 && tiles(128, 128) < 192) {
