@@ -284,3 +284,24 @@ def test_deep_k_beyond_packed_reach(tg):
     tg.gemm(Ad, Bd, Cd, 1.0, 0.0, "f32")
     torch.cuda.synchronize()
     np.testing.assert_array_equal(Cd.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("ldc", [(1 << 25) - 8, (1 << 25) + 8], ids=["ldc_below_2^25", "ldc_above_2^25"])
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_epilogue_row_pitch_near_32bit_offsets(tg, dtype, ldc):
+    # The epilogue reaches C through 32-bit buffer offsets below a row pitch of 2^25
+    # elements and through a plain per-element loop from 2^25 on; both must write
+    # exactly the M x N elements (NaN canaries in the rest of each row stay).
+    M, N, K = 3, 50, 40
+    A, B, C0 = inputs.integer_inputs(M, N, K, seed=42)
+    ref = oracle.gemm(A, B, C0, 1.5, 0.5)
+    store = torch.full((M, ldc), float("nan"), device=DEV)
+    C = store[:, :N]
+    C.copy_(C0.to(DEV))
+    tg.gemm(A.to(DEV), B.to(DEV), C, 1.5, 0.5, dtype)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy().astype(np.float64), ref)
+    assert bool(torch.isnan(store[:, N:N + 1024]).all().item())
+    assert bool(torch.isnan(store[:, -1024:]).all().item())
+    del store
+    torch.cuda.empty_cache()
