@@ -551,9 +551,10 @@ def main():
             "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(tf, 2),
             "peak_tflops": round(PEAK_TFLOPS[dt], 1), "frac_peak": round(tf / PEAK_TFLOPS[dt], 4),
             "schedule": sched, "schedule_key": tg.schedule_key(sched[0]),
-            "packed": info["vec"] == 0,
-            # threads of the main kernel's grid: how a profile tells the paths apart
-            "grid_threads": tiles * 64 * info["WGM"] * info["WGN"]}
+            "packed": info["vec"] == 0, "stream_k": info["split"] == 1,
+            # threads of the main kernel's grid: how a profile tells the paths apart (a
+            # stream-K form launches one resident wave instead, and is told by its name)
+            "grid_threads": None if info["split"] else tiles * 64 * info["WGM"] * info["WGN"]}
 
     # dominant kernel = the path with the largest share of the step
     dom_key = max(per_path, key=lambda k: per_path[k]["avg_ms"])

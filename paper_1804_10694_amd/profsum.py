@@ -25,7 +25,7 @@ import csv
 import json
 from collections import OrderedDict, defaultdict
 
-MAIN_KERNELS = ("gemm_kernel", "packed_kernel", "scaled_kernel")
+MAIN_KERNELS = ("gemm_kernel", "packed_kernel", "packed_sk_kernel", "scaled_kernel")
 PACK_KERNELS = ("pack_rows_kernel", "pack_cols_kernel")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
@@ -90,19 +90,27 @@ def read_bench(path):
 
 
 def paths_by_grid(bench):
+    """Paths by the main kernel's grid (threads); stream-K paths, which launch one
+    resident wave, under the key "sk"."""
     out = {}
     for label, p in bench["paths"].items():
         shape = label.split("_", 1)[1]
-        out.setdefault(p["grid_threads"], []).append((label, p["schedule_key"] + "@" + shape, p))
+        g = "sk" if p.get("stream_k") else p["grid_threads"]
+        out.setdefault(g, []).append((label, p["schedule_key"] + "@" + shape, p))
     return out
 
 
 def match(calls, bench):
-    """{label: (key, [calls])} for the calls whose main kernel grid names one path."""
+    """{label: (key, [calls])} for the calls whose main kernel grid (or, for a
+    stream-K form, kernel name and tile) names one path."""
     grids = paths_by_grid(bench)
     got = defaultdict(list)
     for main, packs in calls:
-        cands = grids.get(main["grid"], [])
+        if "packed_sk_kernel" in main["name"]:
+            tile = lambda p: ",%d,%d," % tuple(int(x) for x in p["schedule_key"].split(":")[2].split("x")[:2])
+            cands = [c for c in grids.get("sk", []) if tile(c[2]) in short_name(main["name"])]
+        else:
+            cands = grids.get(main["grid"], [])
         # paths sharing a grid are told apart by the main kernel's mode (template argument 0/1)
         for label, key, p in cands:
             mode = "1" if label.startswith("x3") else "0"
