@@ -88,7 +88,11 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha,
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation).  Arguments, results and degenerate cases as tgemm, with the
  * same schedule choice except that the cost model is never run (its cached
- * answers, the tuning database and the built-in rule are used).  A packed
+ * answers, the tuning database and the built-in rule are used) and that a
+ * stream-K choice, whose per-tile counters the library allocates, runs as its
+ * whole-tile schedule (the same tiles and K panels, one workgroup per tile:
+ * another summation order, so the result may differ from tgemm's in the last
+ * bits; on exact-integer inputs both are exact).  A packed
  * schedule's packing workspace is a static device array of
  * TGEMM_NOALLOC_SCRATCH_BYTES (128 MiB) in the library's code object, one per
  * device, held from the library's first use on that device until the process
