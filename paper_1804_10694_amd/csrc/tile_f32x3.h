@@ -33,6 +33,9 @@ namespace tg {
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Four floats at a 4-byte aligned address: one 16-byte load instruction (the
+// hardware takes dword-aligned multi-dword loads).
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 

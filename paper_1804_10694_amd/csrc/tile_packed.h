@@ -55,22 +55,23 @@ inline int pack_cols_vec(const void* X, int64_t ld, int es)
 // A-side, one group of 8 consecutive k of row r: X (R x K, row stride ldx)
 // -> P (row stride Kp); zero beyond R and K.  x3: X is float, P / Plo receive
 // the bf16 hi and lo parts.  f32: floats, copied.  bf16 / e4m3: X holds codes,
-// copied.  vec: X and its row stride allow one 8-element vector load per
-// group (16-byte aligned rows; 8-byte for e4m3), used for groups wholly
-// inside the matrix.
+// copied.  A group wholly inside the matrix takes vector loads: float rows
+// always (two 16-byte loads at any 4-byte alignment), code rows when vec says
+// X and its row stride allow one 8-element vector load (16-byte aligned rows;
+// 8-byte for e4m3).
 template <int MODE>
 __device__ __forceinline__ void pack_row_group(const void* X, int64_t ldx, int R, int K, void* P,
                                                void* Plo, int Kp, int r, int k0, bool vec)
 {
     constexpr int ES = src_bytes<MODE>();
-    const bool whole = vec && r < R && k0 + 8 <= K;
+    const bool whole = (ES == 4 || vec) && r < R && k0 + 8 <= K;
     const char* src = static_cast<const char*>(X) + ((int64_t)r * ldx + k0) * ES;
     const int64_t o = (int64_t)r * Kp + k0;
     if (MODE == MODE_F32 || MODE == MODE_X3) {
         f32x4 v0, v1;
         if (whole) {
-            v0 = *reinterpret_cast<const f32x4*>(src);
-            v1 = *reinterpret_cast<const f32x4*>(src + 16);
+            v0 = *reinterpret_cast<const f32x4u*>(src);
+            v1 = *reinterpret_cast<const f32x4u*>(src + 16);
         } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -127,8 +128,9 @@ __device__ __forceinline__ void pack_row_group(const void* X, int64_t ldx, int R
 // matrix); writes: each lane stores 16 consecutive k of one packed row with
 // 16-byte stores.  Zero beyond K and N; nothing written at or beyond Np, and
 // Kp must be a multiple of 16.  256 threads; ends with a barrier, so `tile`
-// can be reused at once.  vec: rows of X are aligned for 4-element vector
-// loads.
+// can be reused at once.  Four elements inside the matrix take one vector
+// load: floats always (16 bytes at any 4-byte alignment), codes when vec says
+// the rows of X are aligned for it.
 template <int MODE>
 __device__ __forceinline__ void pack_col_block(const void* X, int64_t ldx, int K, int N, void* P,
                                                void* Plo, int Np, int Kp, int n0, int k0,
@@ -144,9 +146,9 @@ __device__ __forceinline__ void pack_col_block(const void* X, int64_t ldx, int K
             const int kk = kr + 16 * pass, k = k0 + kk;
             const char* src = static_cast<const char*>(X) + ((int64_t)k * ldx + n) * ES;
             float v[4];
-            if (vec && k < K && n + 4 <= N) {
+            if ((ES == 4 || vec) && k < K && n + 4 <= N) {
                 if (ES == 4) {
-                    const f32x4 x = *reinterpret_cast<const f32x4*>(src);
+                    const f32x4 x = *reinterpret_cast<const f32x4u*>(src);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) v[c] = x[c];
                 } else if (ES == 2) {
