@@ -572,8 +572,13 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         char c = pk ? kPacked : kDirect;
         if (!pk && !g.scale_only && inplace_ok(g, t)) {
             c = g.cfg < 2 ? kInplace : kInplace128;
-            // 16-byte units need aligned rows and no unit across the end of a row
-            g.ip_vec = ((g.cfg & 1) == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
+            // 16-byte units: x3 at any 4-byte aligned address (its loaders switch to
+            // 4-byte loads where a unit would run past the end of the matrix); f32
+            // with aligned rows and no unit across the end of a row
+            if (dtype == TGEMM_F32_BF16X3)
+                g.ip_vec = (reinterpret_cast<uintptr_t>(A[p]) % 4 == 0 && reinterpret_cast<uintptr_t>(B[p]) % 4 == 0);
+            else
+                g.ip_vec = ((g.cfg & 1) == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
         }
         descs.push_back(g);
         cls.push_back(c);

@@ -91,9 +91,17 @@ __device__ __forceinline__ int ip_bslot(int k, int u)
 // A panels from the caller's A (row-major, K-contiguous) into the packed A
 // layout (pk_slot rows of UK units).  A 16-byte load instruction fills 64
 // units, a 4-byte one 16 units (lane l: element l % 4 of unit l / 4).
+// Whether the 16-byte form serves rows of any length (x3): the panels whose
+// 16-byte units would run past the end of the matrix take 4-byte loads.  The
+// f32 forms keep the 16-byte loads for K and N multiples of 4 only, where the
+// extra code would cost the registers of their eight (four) workgroups per CU.
+template <class CF>
+constexpr bool kAnyRowOf = CF::MODE == MODE_X3;
+
 template <class CF, bool VEC>
 struct InplaceA {
     struct Geom {};
+    static constexpr bool kAnyRow = kAnyRowOf<CF>;
     static constexpr int NI = VEC ? CF::A_INSTR : CF::A_INSTR4, UK = CF::UK;
     static constexpr int LOADS = NI;
     static constexpr int W = VEC ? 16 : 4;  // bytes per lane per load
@@ -135,10 +143,33 @@ struct InplaceA {
         const int k0 = panel * CF::BK;
         const __amdgpu_buffer_rsrc_t r = make_rsrc(base + k0 * 4, (rows - 1) * row_bytes + (K - k0) * 4);
         const bool tail = k0 + CF::BK > K;  // uniform
+        if constexpr (VEC && kAnyRow) {
+            if (tail && (K & 3)) {
+                // a 16-byte unit would run past the end of its row: exact 4-byte loads
+                issue4(r, k0, stage);
+                return;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int ig = wave * NI + i;
             lds_load<W>(r, stage + ig * 64 * W, (tail && k0 + ku[i] >= K) ? OOB : voff[i]);
+        }
+    }
+
+    // The panel at k0 with 4-byte loads into the same layout (the offsets of
+    // the 4-byte form, computed here: the tail panel is a tile's last).
+    __device__ __forceinline__ void issue4(__amdgpu_buffer_rsrc_t r, int k0, char* stage) const
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < CF::A_INSTR4; ++i) {
+            const int ig = wave * CF::A_INSTR4 + i;
+            const int slot = ig * 16 + lane / 4;
+            const int row = slot / UK;
+            const int u = (slot % UK) ^ ((row / (16 / UK)) & (UK - 1));
+            const int k = 4 * u + lane % 4;
+            lds_load<4>(r, stage + ig * 64 * 4, k0 + k >= K ? OOB : row * row_bytes + k * 4);
         }
     }
 };
@@ -147,6 +178,7 @@ struct InplaceA {
 // A 16-byte load instruction fills 64 units, a 4-byte one 64 floats.
 template <class CF, bool VEC>
 struct InplaceB {
+    static constexpr bool kAnyRow = kAnyRowOf<CF>;
     static constexpr int NI = VEC ? CF::B_INSTR : CF::B_INSTR4;
     static constexpr int LOADS = NI;
     static constexpr int W = VEC ? 16 : 4;
@@ -181,12 +213,36 @@ struct InplaceB {
     {
         const int k0 = panel * CF::BK;
         const int rows = K - k0 < CF::BK ? K - k0 : CF::BK;
-        const __amdgpu_buffer_rsrc_t r =
-            make_rsrc(base + (int64_t)k0 * row_bytes, (rows - 1) * row_bytes + cols * 4);
+        // With N % 4 != 0 the last 16-byte unit of a row of an edge tile runs
+        // past column N: into the next row of B for every row but the last, so
+        // a panel that does not hold B's last row reads its rows whole (the
+        // extra columns only feed outputs beyond N, which are never written),
+        // and the panel that does takes exact 4-byte loads.
+        const bool ragged = VEC && kAnyRow && (cols & 3);  // uniform
+        if (ragged && k0 + CF::BK >= K) {
+            issue4(make_rsrc(base + (int64_t)k0 * row_bytes, (rows - 1) * row_bytes + cols * 4), stage);
+            return;
+        }
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base + (int64_t)k0 * row_bytes,
+                                                   ragged ? rows * row_bytes : (rows - 1) * row_bytes + cols * 4);
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int ig = wave * NI + i;
             lds_load<W>(r, stage + ig * 64 * W, voff[i]);
+        }
+    }
+
+    // A panel with 4-byte loads into the same layout (offsets computed here).
+    __device__ __forceinline__ void issue4(__amdgpu_buffer_rsrc_t r, char* stage) const
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < CF::B_INSTR4; ++i) {
+            const int ig = wave * CF::B_INSTR4 + i;
+            const int s = ig * 64 + lane;
+            const int k = s / CF::BN, d = s % CF::BN;
+            const int u = (d / 4) ^ (((k / CF::HS) & 1) * 8);
+            lds_load<4>(r, stage + ig * 64 * 4, k * row_bytes + (4 * u + d % 4) * 4);
         }
     }
 };
