@@ -91,17 +91,16 @@ __device__ __forceinline__ int ip_bslot(int k, int u)
 // A panels from the caller's A (row-major, K-contiguous) into the packed A
 // layout (pk_slot rows of UK units).  A 16-byte load instruction fills 64
 // units, a 4-byte one 16 units (lane l: element l % 4 of unit l / 4).
-// Whether the 16-byte form serves rows of any length (x3): the panels whose
-// 16-byte units would run past the end of the matrix take 4-byte loads.  The
-// f32 forms keep the 16-byte loads for K and N multiples of 4 only, where the
-// extra code would cost the registers of their eight (four) workgroups per CU.
-template <class CF>
-constexpr bool kAnyRowOf = CF::MODE == MODE_X3;
-
-template <class CF, bool VEC>
+// ANY: the 16-byte form (VEC) serves rows of any length: the panels whose
+// 16-byte units would run past the end of the matrix take 4-byte loads.
+// Without it the 16-byte form needs K and N multiples of 4; the grouped launch
+// enables it for x3 only (the extra code costs the f32 tiles the registers of
+// their eight or four workgroups per CU, and the back-to-back gemm, whose
+// 16-byte form has aligned dimensions anyway, a split of its loop body).
+template <class CF, bool VEC, bool ANY = false>
 struct InplaceA {
     struct Geom {};
-    static constexpr bool kAnyRow = kAnyRowOf<CF>;
+    static constexpr bool kAnyRow = ANY;
     static constexpr int NI = VEC ? CF::A_INSTR : CF::A_INSTR4, UK = CF::UK;
     static constexpr int LOADS = NI;
     static constexpr int W = VEC ? 16 : 4;  // bytes per lane per load
@@ -176,9 +175,9 @@ struct InplaceA {
 
 // B panels (BK rows of the caller's row-major B) into the k-major LDS layout.
 // A 16-byte load instruction fills 64 units, a 4-byte one 64 floats.
-template <class CF, bool VEC>
+template <class CF, bool VEC, bool ANY = false>
 struct InplaceB {
-    static constexpr bool kAnyRow = kAnyRowOf<CF>;
+    static constexpr bool kAnyRow = ANY;
     static constexpr int NI = VEC ? CF::B_INSTR : CF::B_INSTR4;
     static constexpr int LOADS = NI;
     static constexpr int W = VEC ? 16 : 4;
@@ -370,11 +369,13 @@ struct InplaceOps<CF, MODE_X3> {
 };
 
 // One BM x BN macro-tile of problem `a` (a.A, a.lda, a.B, a.ldb: the caller's
-// matrices) with the in-place pipeline; VEC selects 16-byte loads.
+// matrices) with the in-place pipeline; VEC selects 16-byte loads (for x3 on
+// rows of any length, see InplaceA).
 template <class CF, bool VEC>
 __device__ __forceinline__ void inplace_tile(const PackedArgs& a, int m0, int n0, char* lds)
 {
-    packed_tile<CF, InplaceA<CF, VEC>, InplaceB<CF, VEC>, InplaceOps<CF>>(a, m0, n0, lds);
+    constexpr bool any = VEC && CF::MODE == MODE_X3;
+    packed_tile<CF, InplaceA<CF, VEC, any>, InplaceB<CF, VEC, any>, InplaceOps<CF>>(a, m0, n0, lds);
 }
 
 }  // namespace tg
