@@ -106,12 +106,14 @@ constexpr int kPackedKPad = 32;  // packed K is a multiple of this (the panel de
 // deeper pipelines (measured on MI355X over 512 problems in [16, 2048]^3:
 // 16-deep panels in 2 stages, 8 workgroups per CU, beat 3 stages with 6, 4
 // with 5 and 32-deep panels with 3 to 5 by 5-18%).
-// x3 stops at 6 per CU: its operand split needs more than the 64 registers a
-// wave may hold at 8.
+// f32 stops at 7 per CU and x3 at 6: the 16-byte loads on rows of any length
+// (see InplaceA) and x3's operand split need more than the 64 registers a
+// wave may hold at 8 (f32 with those loads at 7 per CU: 0.879 ms on the
+// 512-problem set, against 0.905 for 16-byte loads on aligned rows only at 8).
 template <int MODE>
 using GroupInplace = ICfg<MODE, 64, 64, 16, 2, 2, 2>;
 template <int MODE>
-constexpr int kInplaceCap = (MODE == MODE_F32) ? 8 : 6;
+constexpr int kInplaceCap = (MODE == MODE_F32) ? 7 : 6;
 template <int MODE>
 constexpr int kInplaceOcc = (160 * 1024) / GroupInplace<MODE>::LDS_BYTES > kInplaceCap<MODE>
                                 ? kInplaceCap<MODE>
@@ -119,13 +121,13 @@ constexpr int kInplaceOcc = (160 * 1024) / GroupInplace<MODE>::LDS_BYTES > kInpl
 constexpr int kInplaceTile = 64;
 // In-place 128 x 128 tiles for the problems whose M and N reach the plan's
 // tile threshold: 4 waves of 64 x 64, the same 16-deep panels in two 16 KB
-// stages; four workgroups per CU (x3: three, for the registers of its operand
-// split).  Each panel byte feeds twice the MFMAs of a 64 x 64 tile, which
-// halves the operand reads from L2 and beyond.
+// stages; three workgroups per CU (for the registers of the 16-byte loads on
+// rows of any length, and x3's operand split).  Each panel byte feeds twice the
+// MFMAs of a 64 x 64 tile, which halves the operand reads from L2 and beyond.
 template <int MODE>
 using GroupInplace128 = ICfg<MODE, 128, 128, 16, 2, 2, 2>;
 template <int MODE>
-constexpr int kInplace128Occ = (MODE == MODE_F32) ? 4 : 3;
+constexpr int kInplace128Occ = 3;
 constexpr int kInplace128Tile = 128;
 
 template <class CF>
@@ -572,13 +574,9 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         char c = pk ? kPacked : kDirect;
         if (!pk && !g.scale_only && inplace_ok(g, t)) {
             c = g.cfg < 2 ? kInplace : kInplace128;
-            // 16-byte units: x3 at any 4-byte aligned address (its loaders switch to
-            // 4-byte loads where a unit would run past the end of the matrix); f32
-            // with aligned rows and no unit across the end of a row
-            if (dtype == TGEMM_F32_BF16X3)
-                g.ip_vec = (reinterpret_cast<uintptr_t>(A[p]) % 4 == 0 && reinterpret_cast<uintptr_t>(B[p]) % 4 == 0);
-            else
-                g.ip_vec = ((g.cfg & 1) == 0 && g.K % 4 == 0 && g.N % 4 == 0) ? 1 : 0;
+            // 16-byte units at any 4-byte aligned address (the loaders switch to
+            // 4-byte loads where a unit would run past the end of the matrix)
+            g.ip_vec = (reinterpret_cast<uintptr_t>(A[p]) % 4 == 0 && reinterpret_cast<uintptr_t>(B[p]) % 4 == 0);
         }
         descs.push_back(g);
         cls.push_back(c);

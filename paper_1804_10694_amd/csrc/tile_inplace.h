@@ -93,10 +93,10 @@ __device__ __forceinline__ int ip_bslot(int k, int u)
 // units, a 4-byte one 16 units (lane l: element l % 4 of unit l / 4).
 // ANY: the 16-byte form (VEC) serves rows of any length: the panels whose
 // 16-byte units would run past the end of the matrix take 4-byte loads.
-// Without it the 16-byte form needs K and N multiples of 4; the grouped launch
-// enables it for x3 only (the extra code costs the f32 tiles the registers of
-// their eight or four workgroups per CU, and the back-to-back gemm, whose
-// 16-byte form has aligned dimensions anyway, a split of its loop body).
+// Without it the 16-byte form needs K and N multiples of 4.  The grouped
+// launch enables it; the back-to-back gemm, whose 16-byte form has aligned
+// dimensions anyway, does not (the unused branch split its loop body and cost
+// it 13%).
 template <class CF, bool VEC, bool ANY = false>
 struct InplaceA {
     struct Geom {};
@@ -369,12 +369,12 @@ struct InplaceOps<CF, MODE_X3> {
 };
 
 // One BM x BN macro-tile of problem `a` (a.A, a.lda, a.B, a.ldb: the caller's
-// matrices) with the in-place pipeline; VEC selects 16-byte loads (for x3 on
-// rows of any length, see InplaceA).
+// matrices) with the in-place pipeline; VEC selects 16-byte loads (on rows of
+// any length, see InplaceA).
 template <class CF, bool VEC>
 __device__ __forceinline__ void inplace_tile(const PackedArgs& a, int m0, int n0, char* lds)
 {
-    constexpr bool any = VEC && CF::MODE == MODE_X3;
+    constexpr bool any = VEC;
     packed_tile<CF, InplaceA<CF, VEC, any>, InplaceB<CF, VEC, any>, InplaceOps<CF>>(a, m0, n0, lds);
 }
 

@@ -121,11 +121,11 @@ def test_inplace_tiles_bit_exact_with_nan_padding(tg, dtype, dims, pad, tile):
     # All problems take the in-place tiles of one size.  A and B sit in buffers
     # `pad` (or pad + 4) columns wider than the matrices, the extra columns NaN: A past K
     # (the row's tail) must read as zero, and B's columns past N only reach accumulator
-    # columns that are never stored.  C's canary columns must stay NaN.  f32: odd
-    # dimensions or a pad of 3 (rows off 16-byte alignment) take the 4-byte loads.  x3
-    # takes 16-byte loads at those 4-byte aligned addresses too (exactness here pins that
-    # the hardware honours them), with 4-byte loads for A's tail panel when K % 4 != 0 and
-    # for the panel holding B's last row on edge tiles when N % 4 != 0.
+    # columns that are never stored.  C's canary columns must stay NaN.  Odd dimensions
+    # and a pad of 3 put rows off 16-byte alignment: the tiles take 16-byte loads at those
+    # 4-byte aligned addresses (exactness here pins that the hardware honours them), with
+    # 4-byte loads for A's tail panel when K % 4 != 0 and for the panel holding B's last
+    # row on edge tiles when N % 4 != 0.
     host = _problem_set(dims, 5400, integer=True)
     As, Bs, Cs, views = [], [], [], []
     for p, (A, B, C0) in enumerate(host):
