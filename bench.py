@@ -450,6 +450,7 @@ def extra_rows(tg, inputs, checks):
             "hbm_gbs_compulsory": round(gbytes / (avg * 1e-3) / 1e9, 1),
             "floor_ms": round(floor_ms, 4), "frac_of_floor": round(floor_ms / avg, 4),
             "tile128_threshold": shape["threshold"], "packed_256_threshold": shape["large"],
+            "tile128_cost_ratio_permille": shape["ratio"],
             "bound": "mfma" if gflops / (PEAK_TFLOPS[dt] * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
             else "hbm"}
         del graph

@@ -325,14 +325,18 @@ int tgemm_conv3x3_packed_shape(int dtype, int i, int* bm, int* bn, int* bk, int*
  * (in-place tiles; 16-byte loads where rows are 16-byte aligned and K and N
  * are multiples of 4, else 4-byte loads), or, for problems whose tile rows
  * exceed the 2^31-byte reach of a buffer offset, register-staged direct
- * tiles.  Plans are cached per shape.  Returns TGEMM_INVALID_VALUE for a negative threshold, otherwise
- * as tgemm_batched.
+ * tiles.  ratio > 0 replaces the threshold by a per-problem choice: a
+ * problem takes 128 x 128 tiles when ratio * (its number of 128 x 128 tiles)
+ * < 1000 * (its number of 64 x 64 tiles), i.e. when the 128 x 128 tiling
+ * costs it less if one such tile costs ratio / 1000 times a 64 x 64 tile.
+ * Plans are cached per shape.  Returns TGEMM_INVALID_VALUE for a negative
+ * threshold or large, or ratio outside [0, 10^6]; otherwise as tgemm_batched.
  */
 int tgemm_batched_with_shape(int64_t count, const int64_t* M, const int64_t* N, const int64_t* K,
                              const float* alpha, const void* const* A, const int64_t* lda,
                              const void* const* B, const int64_t* ldb, const float* beta,
                              float* const* C, const int64_t* ldc, int dtype, int threshold,
-                             int large, void* stream);
+                             int large, int ratio, void* stream);
 
 /*
  * tgemm_batched over `count` problems of one shape at fixed element strides
@@ -352,19 +356,24 @@ int tgemm_batched_strided(int64_t count, int64_t M, int64_t N, int64_t K, float 
 /*
  * Plan-shape autotuner of the grouped launch (project addition; the paper
  * chooses tile sizes by measurement, Section VI-A).  Same arguments as
- * tgemm_batched plus `reps` and two host output pointers.  It times one
+ * tgemm_batched plus `reps` and three host output pointers.  It times one
  * launch of the whole set for every shape (threshold in {0, 64, 96, 160, 256,
  * 512, never} x large in {256, 512, 1024, never}, as in
- * tgemm_batched_with_shape; shapes that give every problem the same tiles
- * are timed once), takes the median of `reps` timed launches after one
- * warm-up, and keeps the fastest for problem sets of these dimensions (M, N,
- * K, alpha == 0 and load width per problem).  Later tgemm_batched calls on
+ * tgemm_batched_with_shape), then the per-problem rule (no packed class) at
+ * the ratio of a least-squares fit of the class costs to those timings (time
+ * = c + a64 * sum of 64 x 64 tiles * (K + 32) + a128 * the same over
+ * 128 x 128 tiles; ratio = 1000 * a128 / a64) and at ratios 1500, 2000, 2500,
+ * 3000 and 3500.  Shapes that give every problem the same tiles are timed once.
+ * Each time is the median of `reps` timed launches after one warm-up; the
+ * fastest shape is kept for problem sets of these dimensions (M, N, K,
+ * alpha == 0 and load width per problem).  Later tgemm_batched calls on
  * such sets use it; cached plans of these dimensions are discarded, so a
  * graph captured over one must be captured again.  C is restored to its
  * contents at entry (the timed launches overwrite it; a device copy of C is
  * allocated for the call).  Synchronises `stream`.  Returns
  * TGEMM_CAPTURE_UNPLANNED while `stream` captures.  On success
- * *threshold_out and *large_out hold the shape chosen (INT32_MAX: never).
+ * *threshold_out, *large_out and *ratio_out hold the shape chosen
+ * (INT32_MAX: never; ratio 0: the threshold rule).
  * reps in [1, 1000].  Without tuning, tgemm_batched uses threshold 96 and
  * no packed class.
  */
@@ -372,7 +381,7 @@ int tgemm_batched_autotune(int64_t count, const int64_t* M, const int64_t* N, co
                            const float* alpha, const void* const* A, const int64_t* lda,
                            const void* const* B, const int64_t* ldb, const float* beta,
                            float* const* C, const int64_t* ldc, int dtype, int reps, void* stream,
-                           int* threshold_out, int* large_out);
+                           int* threshold_out, int* large_out, int* ratio_out);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char* tgemm_status_string(int status);

@@ -4,30 +4,33 @@
 // uneven gemms).
 //
 // Plan (host, once per problem set).  A problem whose M and N both reach the
-// "large" threshold goes to the packed class, every other problem to the
-// direct class:
+// "large" threshold goes to the packed class; every other problem gets 128 x
+// 128 or 64 x 64 tiles, by a threshold on M and N or, per problem, by the
+// tile counts it would have under each and a cost ratio of the two tiles:
 //   - packed class (array packing, Section I): the plan owns a workspace with
 //     the problem's A and B^T in the packed layout of tile_packed.h (rows
 //     padded to 256, K to a multiple of 32); 256 x 256 macro-tiles of 8 waves
 //     stream K panels from it into LDS with direct-to-LDS loads;
-//   - direct class: 128 x 128 macro-tiles when M and N both reach the tile
-//     threshold, 64 x 64 otherwise, with 16-byte or 4-byte global loads as
-//     the operands allow; the tile bodies of tile_f32x3.h load A and B from
-//     the caller's matrices.
-// Both thresholds are built-in defaults unless tgemm_batched_autotune has
-// measured sets of these dimensions.  Within a class, problems are ordered by
-// the work of one of their tiles, largest first, and their tiles numbered
-// consecutively; a tile map (tile -> problem, tile within the problem) and a
-// descriptor table are uploaded to device memory the plan owns.
+//   - in-place classes (128 x 128 and 64 x 64 tiles, tile_inplace.h): K
+//     panels go from the caller's A and B straight into LDS;
+//   - direct class: problems whose tile rows pass the 2^31-byte reach of a
+//     buffer offset take the register-staged tile bodies of tile_f32x3.h.
+// The thresholds and the ratio are built-in defaults unless
+// tgemm_batched_autotune has measured sets of these dimensions.  Within a
+// class, problems are ordered by the work of one of their tiles, largest
+// first, and their tiles numbered consecutively; a tile map (tile ->
+// problem, tile within the problem), one work list per XCD and a descriptor
+// table are uploaded to device memory the plan owns.
 //
-// Launch: the packing kernel (one pass over every packed problem), the packed
-// class's persistent kernel, then the direct class's persistent kernel.  In a
-// persistent kernel workgroup w takes tiles w, w + grid, ... (heavy tiles
-// first, light ones fill the tail).  A launch allocates and uploads nothing,
-// so it can be captured in a HIP graph once the plan exists.
+// Launch: the packing kernel (one pass over every packed problem), then one
+// persistent kernel per non-empty class.  In a persistent kernel the
+// workgroups of each XCD walk that XCD's work list (heavy tiles first, light
+// ones fill the tail).  A launch allocates and uploads nothing, so it can be
+// captured in a HIP graph once the plan exists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -429,22 +432,39 @@ uint64_t fbits(float f)
 }
 
 // Plan shape: problems whose M and N both reach `large` form the packed
-// class; among the rest, `threshold` selects 128 x 128 over 64 x 64 tiles.
+// class.  Among the rest, with ratio == 0, `threshold` selects 128 x 128 over
+// 64 x 64 tiles; with ratio > 0 each problem takes the tile that costs it less
+// by a per-class cost model: a tile of the 128 class costs ratio / 1000 times
+// one of the 64 class at the same K (both scale with K + 32 in the plan's
+// estimate), so 128 x 128 wins when ratio * tiles128 < 1000 * tiles64.
 struct Shape {
     int threshold;
     int large;
+    int ratio;
 };
 constexpr int kNever = INT32_MAX;
 // Default: 128 x 128 direct tiles once both output dimensions fill most of one
 // (fewer, more efficient tiles), 64 x 64 below (less padding); no packed
 // class (on sets of problems in [16, 2048]^3 with beta != 0 its one workgroup
 // per CU leaves the C traffic of short-K tiles exposed: measured on MI355X).
-constexpr Shape kDefaultShape = {96, kNever};
+constexpr Shape kDefaultShape = {96, kNever, 0};
 // Values the tuner times.
 constexpr int kThresholds[] = {0, 64, 96, 160, 256, 512, kNever};
 constexpr int kLarge[] = {256, 512, 1024, kNever};
+// Per-problem rule: cost ratios (per mille) timed besides the one fitted.
+constexpr int kRatios[] = {1500, 2000, 2500, 3000, 3500};
+constexpr int kMaxRatio = 1000000;
 
 bool reaches(const GroupDesc& g, int t) { return g.M >= t && g.N >= t; }
+
+int64_t tile_count(int64_t M, int64_t N, int t) { return ((M + t - 1) / t) * ((N + t - 1) / t); }
+
+// Whether a problem outside the packed class takes 128 x 128 tiles.
+bool takes_128(int64_t M, int64_t N, const Shape& shape)
+{
+    if (shape.ratio > 0) return (int64_t)shape.ratio * tile_count(M, N, 128) < 1000 * tile_count(M, N, 64);
+    return M >= shape.threshold && N >= shape.threshold;
+}
 
 // Whether a direct-class problem with 64 x 64 tiles can take the in-place
 // tiles: a tile's rows of A and a panel's rows of B within the 32-bit reach of
@@ -454,6 +474,39 @@ bool inplace_ok(const GroupDesc& g, int tile)
     return (int64_t)tile * g.lda * 4 <= INT32_MAX &&
            (int64_t)GroupInplace<MODE_F32>::BK * g.ldb * 4 <= INT32_MAX &&
            (int64_t)GroupInplace<MODE_X3>::BK * g.ldb * 4 <= INT32_MAX;
+}
+
+// Ratio a128 / a64 of the least-squares fit  t = c + a64 * s64 + a128 * s128
+// over the timed plan shapes (c = 0 with fewer than four of them); -1 when
+// the equations do not fix two positive costs.
+double fit_ratio(const std::vector<double>& s64, const std::vector<double>& s128, const std::vector<double>& t)
+{
+    const size_t n = t.size();
+    const int u = n >= 4 ? 3 : 2;  // unknowns: (a64, a128[, c])
+    if (n < 2) return -1.0;
+    double G[3][4] = {};          // normal equations, right-hand side in column 3
+    for (size_t i = 0; i < n; ++i) {
+        const double x[3] = {s64[i], s128[i], 1.0};
+        for (int r = 0; r < u; ++r) {
+            for (int c = 0; c < u; ++c) G[r][c] += x[r] * x[c];
+            G[r][3] += x[r] * t[i];
+        }
+    }
+    // Gaussian elimination with partial pivoting
+    for (int c = 0; c < u; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < u; ++r)
+            if (std::fabs(G[r][c]) > std::fabs(G[piv][c])) piv = r;
+        if (!(std::fabs(G[piv][c]) > 1e-12 * std::fabs(G[0][0] + G[1][1] + 1.0))) return -1.0;
+        for (int k = 0; k < 4; ++k) std::swap(G[c][k], G[piv][k]);
+        for (int r = 0; r < u; ++r) {
+            if (r == c) continue;
+            const double f = G[r][c] / G[c][c];
+            for (int k = c; k < 4; ++k) G[r][k] -= f * G[c][k];
+        }
+    }
+    const double a64 = G[0][3] / G[0][0], a128 = G[1][3] / G[1][1];
+    return a64 > 0.0 && a128 > 0.0 ? a128 / a64 : -1.0;
 }
 
 // Tuned plan shapes by problem-set dimensions (pointers, alpha and beta left out).
@@ -566,7 +619,7 @@ int build_plan(int64_t count, const int64_t* M, const int64_t* N, const int64_t*
         if (pk) {
             t = kPackedTile;
         } else if (!g.scale_only) {
-            g.cfg = (reaches(g, shape.threshold) ? 2 : 0) + (vec_ok(A[p], lda[p], B[p], ldb[p], dtype) ? 0 : 1);
+            g.cfg = (takes_128(g.M, g.N, shape) ? 2 : 0) + (vec_ok(A[p], lda[p], B[p], ldb[p], dtype) ? 0 : 1);
             t = kGroupTile[g.cfg];
         }
         g.tiles_m = (int)((M[p] + t - 1) / t);
@@ -797,11 +850,12 @@ int batched_run(int64_t count, const int64_t* M, const int64_t* N, const int64_t
 
     // key of the problem set (and of a forced shape)
     std::vector<uint64_t> key;
-    key.reserve((size_t)count * 11 + 4);
+    key.reserve((size_t)count * 11 + 5);
     key.push_back((uint64_t)count);
     key.push_back((uint64_t)dtype);
     key.push_back(forced ? (uint64_t)(uint32_t)forced->threshold + 1 : 0u);
     key.push_back(forced ? (uint64_t)(uint32_t)forced->large + 1 : 0u);
+    key.push_back(forced ? (uint64_t)(uint32_t)forced->ratio + 1 : 0u);
     for (int64_t p = 0; p < count; ++p) {
         key.push_back((uint64_t)M[p]);
         key.push_back((uint64_t)N[p]);
@@ -845,7 +899,7 @@ int batched_run(int64_t count, const int64_t* M, const int64_t* N, const int64_t
             plan.key = key;
             plan.dims = dk;
             rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype,
-                            Shape{shape.threshold, kNever}, &plan);
+                            Shape{shape.threshold, kNever, shape.ratio}, &plan);
         }
         if (rc != TGEMM_SUCCESS) {
             free_plan(plan);
@@ -953,10 +1007,10 @@ extern "C" int tgemm_batched_with_shape(int64_t count, const int64_t* M, const i
                                         const int64_t* K, const float* alpha, const void* const* A,
                                         const int64_t* lda, const void* const* B, const int64_t* ldb,
                                         const float* beta, float* const* C, const int64_t* ldc,
-                                        int dtype, int threshold, int large, void* stream)
+                                        int dtype, int threshold, int large, int ratio, void* stream)
 {
-    if (threshold < 0 || large < 0) return TGEMM_INVALID_VALUE;
-    const tg::Shape shape{threshold, large};
+    if (threshold < 0 || large < 0 || ratio < 0 || ratio > tg::kMaxRatio) return TGEMM_INVALID_VALUE;
+    const tg::Shape shape{threshold, large, ratio};
     return tg::batched_run(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, &shape,
                            static_cast<hipStream_t>(stream));
 }
@@ -966,14 +1020,15 @@ extern "C" int tgemm_batched_autotune(int64_t count, const int64_t* M, const int
                                       const int64_t* lda, const void* const* B, const int64_t* ldb,
                                       const float* beta, float* const* C, const int64_t* ldc,
                                       int dtype, int reps, void* stream, int* threshold_out,
-                                      int* large_out)
+                                      int* large_out, int* ratio_out)
 {
     using namespace tg;
-    if (reps < 1 || reps > 1000 || !threshold_out || !large_out) return TGEMM_INVALID_VALUE;
+    if (reps < 1 || reps > 1000 || !threshold_out || !large_out || !ratio_out) return TGEMM_INVALID_VALUE;
     int rc = validate_set(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
     if (rc != TGEMM_SUCCESS) return rc;
     *threshold_out = kDefaultShape.threshold;
     *large_out = kDefaultShape.large;
+    *ratio_out = kDefaultShape.ratio;
     if (count == 0) return TGEMM_SUCCESS;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1012,53 +1067,80 @@ extern "C" int tgemm_batched_autotune(int64_t count, const int64_t* M, const int
     Shape best = kDefaultShape;
     float best_ms = 0.f;
     std::vector<std::vector<int>> seen;  // per-problem configurations already timed
+    // Per-class cost fit: each timed shape without a packed class gives one
+    // equation  time = c + a64 * S64 + a128 * S128,  S = sum over the class's
+    // problems of tiles * (K + 32).
+    std::vector<double> fit_s64, fit_s128, fit_t;
+    // times one candidate (skipped if it gives every problem the tiles of a
+    // candidate already timed); false on a launch error
+    auto trial = [&](const Shape& cand) {
+        std::vector<int> cfgs;
+        double s64 = 0.0, s128 = 0.0;
+        for (int64_t p = 0; p < count; ++p) {
+            const bool pk = M[p] >= cand.large && N[p] >= cand.large;
+            const bool big = takes_128(M[p], N[p], cand);
+            cfgs.push_back(pk ? 2 : big ? 1 : 0);
+            if (pk || M[p] == 0 || N[p] == 0 || K[p] == 0 || alpha[p] == 0.f) continue;
+            (big ? s128 : s64) += (double)tile_count(M[p], N[p], big ? 128 : 64) * (double)(K[p] + 32);
+        }
+        if (std::find(seen.begin(), seen.end(), cfgs) != seen.end()) return true;
+        seen.push_back(cfgs);
+        Plan plan;
+        rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cand, &plan);
+        if (rc == TGEMM_ALLOC_FAILED && cand.large != kNever) {
+            // no room for this shape's packing workspace: not a candidate
+            free_plan(plan);
+            rc = TGEMM_SUCCESS;
+            return true;
+        }
+        if (rc != TGEMM_SUCCESS) {
+            free_plan(plan);
+            return false;
+        }
+        std::vector<float> times;
+        rc = launch_plan(plan, s);  // warm-up
+        for (int r = 0; r < reps && rc == TGEMM_SUCCESS; ++r) {
+            (void)hipEventRecord(e0, s);
+            rc = launch_plan(plan, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = TGEMM_LAUNCH_FAILED;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            times.push_back(ms);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess && rc == TGEMM_SUCCESS) rc = TGEMM_LAUNCH_FAILED;
+        free_plan(plan);
+        if (rc != TGEMM_SUCCESS) return false;
+        std::sort(times.begin(), times.end());
+        const float med = times[times.size() / 2];
+        if (cand.large == kNever) {
+            fit_s64.push_back(s64);
+            fit_s128.push_back(s128);
+            fit_t.push_back(med);
+        }
+        if (!found || med < best_ms) {
+            found = true;
+            best = cand;
+            best_ms = med;
+        }
+        return true;
+    };
     rc = copy_c(true) ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
     for (int large : kLarge)
-        for (int threshold : kThresholds) {
-            if (rc != TGEMM_SUCCESS) break;
-            // shapes that give every problem the same tiles are timed once
-            std::vector<int> cfgs;
-            for (int64_t p = 0; p < count; ++p) {
-                const bool pk = M[p] >= large && N[p] >= large;
-                cfgs.push_back(pk ? 2 : (M[p] >= threshold && N[p] >= threshold ? 1 : 0));
-            }
-            if (std::find(seen.begin(), seen.end(), cfgs) != seen.end()) continue;
-            seen.push_back(cfgs);
-            const Shape cand{threshold, large};
-            Plan plan;
-            rc = build_plan(count, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cand, &plan);
-            if (rc == TGEMM_ALLOC_FAILED && large != kNever) {
-                // no room for this shape's packing workspace: not a candidate
-                free_plan(plan);
-                rc = TGEMM_SUCCESS;
-                continue;
-            }
-            if (rc != TGEMM_SUCCESS) {
-                free_plan(plan);
-                break;
-            }
-            std::vector<float> times;
-            rc = launch_plan(plan, s);  // warm-up
-            for (int r = 0; r < reps && rc == TGEMM_SUCCESS; ++r) {
-                (void)hipEventRecord(e0, s);
-                rc = launch_plan(plan, s);
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) rc = TGEMM_LAUNCH_FAILED;
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                times.push_back(ms);
-            }
-            if (hipStreamSynchronize(s) != hipSuccess && rc == TGEMM_SUCCESS) rc = TGEMM_LAUNCH_FAILED;
-            free_plan(plan);
-            if (rc != TGEMM_SUCCESS) break;
-            std::sort(times.begin(), times.end());
-            const float med = times[times.size() / 2];
-            if (!found || med < best_ms) {
-                found = true;
-                best = cand;
-                best_ms = med;
-            }
-        }
+        for (int threshold : kThresholds)
+            if (rc != TGEMM_SUCCESS || !trial(Shape{threshold, large, 0})) goto done;
+    {
+        // per-problem rule: the ratio a128 / a64 of the least-squares fit
+        // (with a constant term when there are enough equations), then the
+        // fixed ratios
+        std::vector<int> ratios;
+        const double r = fit_ratio(fit_s64, fit_s128, fit_t);
+        if (r > 0.0 && r * 1000.0 < kMaxRatio) ratios.push_back((int)(r * 1000.0 + 0.5));
+        ratios.insert(ratios.end(), std::begin(kRatios), std::end(kRatios));
+        for (int ratio : ratios)
+            if (!trial(Shape{0, kNever, ratio})) goto done;
+    }
+done:
     if (rc == TGEMM_SUCCESS && !copy_c(false)) rc = TGEMM_LAUNCH_FAILED;
     if (hipStreamSynchronize(s) != hipSuccess && rc == TGEMM_SUCCESS) rc = TGEMM_LAUNCH_FAILED;
     if (saved) (void)hipFree(saved);
@@ -1079,6 +1161,7 @@ extern "C" int tgemm_batched_autotune(int64_t count, const int64_t* M, const int
     }
     *threshold_out = best.threshold;
     *large_out = best.large;
+    *ratio_out = best.ratio;
     return TGEMM_SUCCESS;
 }
 

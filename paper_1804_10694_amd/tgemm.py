@@ -52,9 +52,9 @@ lib.tgemm_contract.argtypes = [_i32, _p, _p, _p, _i32, _p, _p, _p, _i32, _p, _p,
 lib.tgemm_gemm2.argtypes = [_i64, _i64, _i64, _i64, _f32, _p, _i64, _p, _i64, _i32, _p, _i64, _f32, _p, _i64,
                             _i32, _p]
 lib.tgemm_batched_with_shape.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64,
-                                         _pf32, _pp, _pi64, _i32, _i32, _i32, _p]
+                                         _pf32, _pp, _pi64, _i32, _i32, _i32, _i32, _p]
 lib.tgemm_batched_autotune.argtypes = [_i64, _pi64, _pi64, _pi64, _pf32, _pp, _pi64, _pp, _pi64, _pf32,
-                                       _pp, _pi64, _i32, _i32, _p, _pi32, _pi32]
+                                       _pp, _pi64, _i32, _i32, _p, _pi32, _pi32, _pi32]
 lib.tgemm_status_string.argtypes = [_i32]
 lib.tgemm_status_string.restype = ctypes.c_char_p
 lib.tgemm_set_policy.argtypes = [ctypes.c_char_p]
@@ -288,13 +288,14 @@ def _arr(ctype, values):
 def gemm_batched(As, Bs, Cs, alphas, betas, dtype="f32", stream=None, shape=None):
     """Grouped gemm over lists of tensors (tgemm_batched): C_p = a_p A_p B_p + b_p C_p.
     shape: None (tuned or default plan shape) or {"threshold": T, "large": L}
-    (tgemm_batched_with_shape)."""
+    with an optional "ratio" (per-problem rule, per mille; tgemm_batched_with_shape)."""
     args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
     if shape is None:
         _check(lib.tgemm_batched(*args, _stream_handle(stream)), "tgemm_batched")
     else:
         _check(lib.tgemm_batched_with_shape(*args, int(shape["threshold"]), int(shape["large"]),
-                                            _stream_handle(stream)), "tgemm_batched_with_shape")
+                                            int(shape.get("ratio", 0)), _stream_handle(stream)),
+               "tgemm_batched_with_shape")
 
 
 def _batched_args(As, Bs, Cs, alphas, betas, dtype):
@@ -317,12 +318,13 @@ def _batched_args(As, Bs, Cs, alphas, betas, dtype):
 
 def gemm_batched_autotune(As, Bs, Cs, alphas, betas, dtype="f32", reps=5, stream=None):
     """Plan-shape tuning of a grouped set (tgemm_batched_autotune); returns
-    {"threshold": T, "large": L} (2**31 - 1: never)."""
+    {"threshold": T, "large": L, "ratio": R} (2**31 - 1: never; R = 0: the
+    threshold rule, else the per-problem rule at cost ratio R / 1000)."""
     args = _batched_args(As, Bs, Cs, alphas, betas, dtype)
-    thr, large = ctypes.c_int32(), ctypes.c_int32()
+    thr, large, ratio = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib.tgemm_batched_autotune(*args, reps, _stream_handle(stream), ctypes.byref(thr),
-                                      ctypes.byref(large)), "tgemm_batched_autotune")
-    return {"threshold": thr.value, "large": large.value}
+                                      ctypes.byref(large), ctypes.byref(ratio)), "tgemm_batched_autotune")
+    return {"threshold": thr.value, "large": large.value, "ratio": ratio.value}
 
 
 CONV_AUTO, CONV_DIRECT, CONV_PACKED = 0, 1, 2

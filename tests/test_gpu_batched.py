@@ -296,6 +296,7 @@ def test_autotune_restores_c_and_tuned_plan_is_exact(tg, dtype):
     torch.cuda.synchronize()
     print(f"{dtype}: tuned threshold {t}", flush=True)
     assert t["threshold"] in (0, 64, 96, 160, 256, 512, NEVER) and t["large"] in (256, 512, 1024, NEVER)
+    assert t["ratio"] == 0 or (t["large"] == NEVER and 0 < t["ratio"] <= 10**6)
     for p, (b, c) in enumerate(zip(before, Cs)):
         assert torch.equal(b, c), f"C of problem {p} not restored"
     tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype)
@@ -312,6 +313,46 @@ def test_autotune_and_forced_shape_reject_bad_arguments(tg):
         tg.gemm_batched_autotune([A], [A], [A.clone()], [1.0], [0.0], "f32", reps=0)
     with pytest.raises(tg.TgemmError):
         tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32", shape={"threshold": -1, "large": 0})
+    for ratio in (-1, 10**6 + 1):
+        with pytest.raises(tg.TgemmError):
+            tg.gemm_batched([A], [A], [A.clone()], [1.0], [0.0], "f32",
+                            shape={"threshold": 0, "large": NEVER, "ratio": ratio})
+
+
+@pytest.mark.parametrize("ratio", [1, 2000, 3000, 10**6])
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_per_problem_rule_is_exact(tg, dtype, ratio):
+    # The per-problem rule gives each problem 128 x 128 or 64 x 64 in-place tiles by
+    # comparing its tile counts (ratio 1: every problem 128 x 128; 10^6: every problem
+    # 64 x 64; 2000 and 3000 split this set between the two).  Bit-exact on integers,
+    # C restored between shapes, and the graph replay equals the eager call.
+    dims = np.array([(300, 260, 70), (130, 500, 33), (40, 500, 45), (200, 129, 17), (64, 64, 64),
+                     (257, 390, 101), (16, 16, 16), (129, 129, 40), (70, 390, 90), (390, 70, 90)])
+    # tiles (64, 128): (25, 9), (24, 8), (8, 4), (12, 4), (1, 1), (35, 12), (1, 1), (9, 4),
+    # (14, 4), (14, 4): ratio 2000 puts problems 0, 1, 3, 5, 7, 8 and 9 on 128 x 128
+    # tiles, ratio 3000 only problems 8 and 9
+    host = _problem_set(dims, 5400, integer=True)
+    alphas, betas = [1.0] * len(dims), [0.5] * len(dims)
+    As = [h[0].to(DEV) for h in host]
+    Bs = [h[1].to(DEV) for h in host]
+    Cs = [h[2].clone().to(DEV) for h in host]
+    shape = {"threshold": NEVER, "large": NEVER, "ratio": ratio}
+    tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape=shape)
+    torch.cuda.synchronize()
+    refs = [oracle.gemm(h[0], h[1], h[2], 1.0, 0.5) for h in host]
+    for p in range(len(dims)):
+        np.testing.assert_array_equal(Cs[p].cpu().numpy().astype(np.float64), refs[p],
+                                      err_msg=f"problem {p} {dims[p]}")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tg.gemm_batched(As, Bs, Cs, alphas, betas, dtype, shape=shape)
+    for c, h in zip(Cs, host):
+        c.copy_(h[2].to(DEV))
+    graph.replay()
+    torch.cuda.synchronize()
+    for p in range(len(dims)):
+        np.testing.assert_array_equal(Cs[p].cpu().numpy().astype(np.float64), refs[p],
+                                      err_msg=f"replay, problem {p} {dims[p]}")
 
 
 # small products (M, N <= 16 and <= 32: one wave each) and planned ones
