@@ -552,7 +552,7 @@ def main():
             "avg_ms": round(avg, 4), "median_ms": round(med, 4), "tflops": round(tf, 2),
             "peak_tflops": round(PEAK_TFLOPS[dt], 1), "frac_peak": round(tf / PEAK_TFLOPS[dt], 4),
             "schedule": sched, "schedule_key": tg.schedule_key(sched[0]),
-            "packed": info["vec"] == 0, "stream_k": info["split"] == 1,
+            "packed": info["vec"] == 0, "stream_k": info["split"] == 1, "inplace": info["inplace"] == 1,
             # threads of the main kernel's grid: how a profile tells the paths apart (a
             # stream-K form launches one resident wave instead, and is told by its name)
             "grid_threads": None if info["split"] else tiles * 64 * info["WGM"] * info["WGN"]}
@@ -566,7 +566,8 @@ def main():
     # the events, and so `achieved`, cover the whole call
     roofline = {"bound": "mfma", "kernel": dom_key, "kernel_symbol": sym,
                 "kernels_per_call": (["pack_rows_kernel", "pack_cols_kernel", "packed_kernel"]
-                                     if dom["packed"] else ["gemm_kernel"]),
+                                     if dom["packed"] else ["inplace_gemm_kernel"] if dom["inplace"]
+                                     else ["gemm_kernel"]),
                 "achieved": dom["tflops"],
                 "peak": dom["peak_tflops"], "unit": "TFLOP/s",
                 "frac": round(dom["tflops"] / dom["peak_tflops"], 4),

@@ -398,8 +398,8 @@ const char* tgemm_status_string(int status);
 int tgemm_set_policy(const char* policy);
 
 /* Number of compiled schedules and the parameters of one of them.
- * info receives 10 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes,
- * split, mfma.
+ * info receives 11 ints: dtype, BM, BN, BK, waves_m, waves_n, vec, lds_bytes,
+ * split, mfma, inplace.
  * vec = 4: 16-byte global loads (16-byte aligned bases, row strides multiple of
  * 16 bytes); vec = 1: 4-byte loads (any alignment); vec = 0: packed operands
  * (a pre-pass copies A and B^T, converted and zero-padded, into a workspace
@@ -413,6 +413,11 @@ int tgemm_set_policy(const char* policy);
  * mfma = 32: the MFMAs compute 32 x 32 output blocks (v_mfma_f32_32x32x2f32,
  * 32x32x16_bf16, 32x32x64_f8f6f4); mfma = 16: 16 x 16 blocks (16x16x4f32,
  * 16x16x32_bf16, 16x16x128_f8f6f4; packed schedules only).
+ * inplace = 1 (f32 and x3, vec = 1): no packing pass; each tile's K panels go
+ * from the caller's A and B straight into LDS with direct-to-LDS buffer loads
+ * (16 bytes at any 4-byte alignment), several workgroups per CU; a problem
+ * whose BM rows of A or BK rows of B span 2^31 bytes or more is
+ * TGEMM_NOT_SUPPORTED for it (tgemm then takes the rule's direct schedule).
  * Host-only: no HIP call. */
 int tgemm_schedule_count(void);
 int tgemm_schedule_info(int schedule_id, int* info);

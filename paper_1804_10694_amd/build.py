@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtgemm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "gemm_packed.hip", "batched.hip", "tune.hip", "mlp.hip",
+SOURCES = ["gemm_tile.hip", "gemm_scaled.hip", "gemm_packed.hip", "gemm_inplace.hip", "batched.hip", "tune.hip", "mlp.hip",
            "costmodel.hip", "conv.hip", "gemm2.hip", "contract.hip", "peak.hip",
            "registry.cpp", "api.cpp", "select.cpp"]
 

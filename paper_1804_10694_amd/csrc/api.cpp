@@ -149,6 +149,7 @@ int run_gemm(int id, int64_t M, int64_t N, int64_t K, float alpha, const void* A
         return run_packed(pid, M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc,
                           group_m, xcd_remap, stream);
     const SchedDesc& d = schedule(id);
+    if (d.inplace && !inplace_reach_ok(d, lda, ldb)) return TGEMM_NOT_SUPPORTED;
     GemmArgs a = make_args(d, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, group_m, xcd_remap);
     if ((int64_t)a.tiles_m * a.tiles_n > INT32_MAX) return TGEMM_NOT_SUPPORTED;
     return launch_gemm(d, a, stream) == hipSuccess ? TGEMM_SUCCESS : TGEMM_LAUNCH_FAILED;
@@ -198,9 +199,10 @@ int tgemm(int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t l
         else
             rc = run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m,
                           ch.xcd_remap, s);
-        // a packed schedule whose workspace would have to grow under capture: use the
+        // a packed schedule whose workspace would have to grow under capture, or an
+        // in-place one whose rows lie past the reach of its buffer offsets: use the
         // rule's schedule without packing instead
-        if (rc != TGEMM_CAPTURE_UNPLANNED) return rc;
+        if (rc != TGEMM_CAPTURE_UNPLANNED && !(rc == TGEMM_NOT_SUPPORTED && schedule(ch.id).inplace)) return rc;
         if ((rc = direct_schedule(M, N, K, dtype, vok, &ch)) != TGEMM_SUCCESS) return rc;
     }
     return rc;
@@ -290,6 +292,7 @@ int tgemm_schedule_info(int id, int* info)
     info[7] = d.lds_bytes;
     info[8] = d.split;
     info[9] = d.mfma;
+    info[10] = d.inplace;
     return TGEMM_SUCCESS;
 }
 

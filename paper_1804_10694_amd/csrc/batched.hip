@@ -102,35 +102,15 @@ using GroupPacked = PCfg<MODE, 256, 256, 32, 2, 4, 2>;
 constexpr int kPackedTile = 256;
 constexpr int kPackedKPad = 32;  // packed K is a multiple of this (the panel depth)
 
-// The in-place class's configuration: 64 x 64 macro-tiles of 4 waves whose K
-// panels go straight from the caller's A and B into LDS (tile_inplace.h),
-// 16-deep panels in two 8 KB stages, so that eight workgroups fit per CU: with
-// K of a few hundred, workgroups in flight hide the panel latency better than
-// deeper pipelines (measured on MI355X over 512 problems in [16, 2048]^3:
-// 16-deep panels in 2 stages, 8 workgroups per CU, beat 3 stages with 6, 4
-// with 5 and 32-deep panels with 3 to 5 by 5-18%).
-// f32 stops at 7 per CU and x3 at 6: the 16-byte loads on rows of any length
-// (see InplaceA) and x3's operand split need more than the 64 registers a
-// wave may hold at 8 (f32 with those loads at 7 per CU: 0.879 ms on the
-// 512-problem set, against 0.905 for 16-byte loads on aligned rows only at 8).
+// The in-place classes take the tile configurations of tile_inplace.h
+// (InplaceCfg64 / InplaceCfg128 and their occupancies).
 template <int MODE>
-using GroupInplace = ICfg<MODE, 64, 64, 16, 2, 2, 2>;
+using GroupInplace = InplaceCfg64<MODE>;
 template <int MODE>
-constexpr int kInplaceCap = (MODE == MODE_F32) ? 7 : 6;
+using GroupInplace128 = InplaceCfg128<MODE>;
 template <int MODE>
-constexpr int kInplaceOcc = (160 * 1024) / GroupInplace<MODE>::LDS_BYTES > kInplaceCap<MODE>
-                                ? kInplaceCap<MODE>
-                                : (160 * 1024) / GroupInplace<MODE>::LDS_BYTES;
+constexpr int kInplaceOcc = kInplace64Occ<MODE>;
 constexpr int kInplaceTile = 64;
-// In-place 128 x 128 tiles for the problems whose M and N reach the plan's
-// tile threshold: 4 waves of 64 x 64, the same 16-deep panels in two 16 KB
-// stages; three workgroups per CU (for the registers of the 16-byte loads on
-// rows of any length, and x3's operand split).  Each panel byte feeds twice the
-// MFMAs of a 64 x 64 tile, which halves the operand reads from L2 and beyond.
-template <int MODE>
-using GroupInplace128 = ICfg<MODE, 128, 128, 16, 2, 2, 2>;
-template <int MODE>
-constexpr int kInplace128Occ = 3;
 constexpr int kInplace128Tile = 128;
 
 template <class CF>

@@ -75,7 +75,7 @@ void cost_features(int64_t M, int64_t N, int64_t K, int dtype, const SchedDesc& 
     f[i++] = (float)lg2(d.BM);
     f[i++] = (float)lg2(d.BN);
     f[i++] = (float)lg2(d.BK);
-    f[i++] = d.vec == 4 ? 1.f : (d.vec == 0 ? 2.f : 0.f);          // load width / packed
+    f[i++] = d.inplace ? 3.f : d.vec == 4 ? 1.f : (d.vec == 0 ? 2.f : 0.f);  // load width / packed / in-place
     f[i++] = (float)lg2(group_m);
     f[i++] = xcd ? 1.f : 0.f;
     f[i++] = (float)lg2(tiles);

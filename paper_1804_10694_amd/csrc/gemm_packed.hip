@@ -681,10 +681,14 @@ extern "C" int tgemm_noalloc(int64_t M, int64_t N, int64_t K, float alpha, const
     if ((rc = select_schedule(M, N, K, dtype, vok, &ch, false)) != TGEMM_SUCCESS) return rc;
     const bool scaled = (dtype == TGEMM_BF16 || dtype == TGEMM_FP8_E4M3);
     const int pid = packed_index(ch.id);
-    if (pid < 0) {  // direct schedules use no workspace
+    if (pid < 0) {  // direct and in-place schedules use no workspace
         if (scaled)
             return run_scaled(M, N, K, alpha, A, lda, nullptr, B, ldb, nullptr, beta, C, ldc, dtype, ch.id,
                               ch.group_m, ch.xcd_remap, s);
+        rc = run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m, ch.xcd_remap, s);
+        // an in-place schedule whose rows lie past the reach of its buffer offsets
+        if (rc != TGEMM_NOT_SUPPORTED || !schedule(ch.id).inplace) return rc;
+        if ((rc = direct_schedule(M, N, K, dtype, vok, &ch)) != TGEMM_SUCCESS) return rc;
         return run_gemm(ch.id, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ch.group_m, ch.xcd_remap, s);
     }
     if (!packed_k_ok(K, dtype)) return TGEMM_NOT_SUPPORTED;

@@ -4,7 +4,7 @@
 namespace tg {
 
 namespace {
-constexpr int kParts = 3;
+constexpr int kParts = 4;
 struct Table {
     const SchedDesc* parts[kParts];
     int counts[kParts];
@@ -14,7 +14,8 @@ struct Table {
         parts[0] = tile_schedules(&counts[0]);
         parts[1] = scaled_schedules(&counts[1]);
         parts[2] = packed_schedules(&counts[2]);
-        total = counts[0] + counts[1] + counts[2];
+        parts[3] = inplace_schedules(&counts[3]);
+        total = counts[0] + counts[1] + counts[2] + counts[3];
     }
 };
 
@@ -41,7 +42,7 @@ int packed_index(int id)
 {
     const Table& t = table();
     const int first = t.counts[0] + t.counts[1];
-    return (id >= first && id < t.total) ? id - first : -1;
+    return (id >= first && id < first + t.counts[2]) ? id - first : -1;
 }
 
 }  // namespace tg

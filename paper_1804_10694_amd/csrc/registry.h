@@ -18,6 +18,8 @@ struct SchedDesc {
     int split = 0;  // 1: stream-K (packed schedules): the (tile, K panel) iterations are split
                     // evenly over one wave of resident workgroups
     int mfma = 32;  // MFMA block: 32 (32 x 32 outputs) or 16 (16 x 16)
+    int inplace = 0;  // 1: K panels go from the caller's A and B straight into LDS
+                      // (direct-to-LDS loads, any 4-byte alignment; vec = 1)
 };
 
 // All compiled schedules, ids 0..num_schedules()-1 (tables of every kernel
@@ -29,6 +31,10 @@ const SchedDesc& schedule(int id);
 const SchedDesc* tile_schedules(int* n);    // F32 and split-bf16x3
 const SchedDesc* scaled_schedules(int* n);  // bf16 and fp8 with per-tile scales
 const SchedDesc* packed_schedules(int* n);  // packed-operand f32, x3, bf16, fp8
+const SchedDesc* inplace_schedules(int* n); // in-place f32 and x3 (gemm_inplace.hip)
+// Whether an in-place schedule reaches every row it loads with 32-bit buffer
+// offsets for these row strides.
+bool inplace_reach_ok(const SchedDesc& d, int64_t lda, int64_t ldb);
 
 // Packed schedules (gemm_packed.hip): index within packed_schedules().
 int run_packed(int pid, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,

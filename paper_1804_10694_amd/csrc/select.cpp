@@ -110,13 +110,14 @@ bool dense_vec_ok(int64_t N, int64_t K, int dtype)
     return (K * es) % 16 == 0 && (N * es) % 16 == 0;
 }
 
-int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds, int mfma, int split)
+int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM, int WGN, int lds, int mfma, int split,
+                  int inplace)
 {
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         if (d.dtype == dtype && d.BM == BM && d.BN == BN && d.BK == BK && d.vec == vec &&
             d.WGM == WGM && d.WGN == WGN && (lds < 0 || d.lds_bytes == lds) && d.split == split &&
-            d.mfma == mfma)
+            d.mfma == mfma && d.inplace == inplace)
             return i;
     }
     return -1;
@@ -195,6 +196,30 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    at least 8 K panels per workgroup of the stream-K wave and enough
     //    tiles (16 and 8) that few workgroups share one.
     const bool narrow = (dtype == TGEMM_F32 || dtype == TGEMM_F32_BF16X3) && (M <= 128 || N <= 128);
+    // f32 below the size of the large packed tiles (under 1536 tiles of
+    // 128 x 256) takes in-place tiles when they give enough workgroups: at
+    // least 1000 tiles of 64 x 64, or 100 with K <= 2048 (deeper problems with
+    // few tiles keep stream-K, which spreads K over every CU).  No packing
+    // pass, and seven (64 x 64) or three (128 x 128) workgroups per CU; 128 x
+    // 128 when its tiles fill at least 60% of their waves of 768.  Measured on
+    // MI355X over 24 shapes in [256, 8192]: f32 against the best of the
+    // previous rule and the four in-place forms, geometric mean 0.857 -> 0.955
+    // (4097 x 3001 x 2053: 0.57 -> 0.47 ms; 4096^3 1.15 -> 1.00; 3000^3 0.61 ->
+    // 0.51; 5000^3 even; 8192^3 keeps the packed tiles).  x3 keeps its packed
+    // and direct tiles, which beat the in-place ones on 22 of those shapes.
+    if (dtype == TGEMM_F32 && !narrow && tiles(128, 256) < 1536 &&
+        (tiles(64, 64) >= 1000 || (K <= 2048 && tiles(64, 64) >= 100))) {
+        const int64_t t = tiles(128, 128);
+        const double f = (double)t / (double)(((t + 767) / 768) * 768);
+        const int id = f >= 0.6 ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
+                                : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
+        if (id >= 0) {
+            out->id = id;
+            out->group_m = 8;
+            out->xcd_remap = 0;
+            return TGEMM_SUCCESS;
+        }
+    }
     if (K >= 512 && packed_k_ok(K, dtype) && !narrow) {
         int id = -1;
         const int64_t panels16 = (K + 15) / 16, panels32 = (K + 31) / 32;

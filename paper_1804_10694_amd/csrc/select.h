@@ -29,9 +29,9 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
 int direct_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowed, Choice* out);
 
 // Index of the compiled schedule with these parameters, or -1 (split: 1 for
-// the stream-K form of a packed schedule).
+// the stream-K form of a packed schedule; inplace: 1 for an in-place one).
 int find_schedule(int dtype, int BM, int BN, int BK, int vec, int WGM = 2, int WGN = 2, int lds = -1,
-                  int mfma = 32, int split = 0);
+                  int mfma = 32, int split = 0, int inplace = 0);
 
 // Tuned choices (filled by the autotuner and by the database loader).
 void register_tuned(int dtype, int64_t M, int64_t N, int64_t K, int vec, const Choice& c, double ms);

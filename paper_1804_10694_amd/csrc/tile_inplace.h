@@ -68,6 +68,34 @@ struct ICfg {
     static_assert(LDS_BYTES <= 160 * 1024, "LDS");
 };
 
+// 64 x 64 in-place tiles: 4 waves, 16-deep panels in two 8 KB stages, so that
+// eight workgroups fit per CU: with K of a few hundred, workgroups in flight
+// hide the panel latency better than deeper pipelines (measured on MI355X
+// over 512 grouped problems in [16, 2048]^3:
+// 16-deep panels in 2 stages, 8 workgroups per CU, beat 3 stages with 6, 4
+// with 5 and 32-deep panels with 3 to 5 by 5-18%).
+// f32 stops at 7 per CU and x3 at 6: the 16-byte loads on rows of any length
+// (see InplaceA) and x3's operand split need more than the 64 registers a
+// wave may hold at 8 (f32 with those loads at 7 per CU: 0.879 ms on the
+// 512-problem set, against 0.905 for 16-byte loads on aligned rows only at 8).
+template <int MODE>
+using InplaceCfg64 = ICfg<MODE, 64, 64, 16, 2, 2, 2>;
+template <int MODE>
+constexpr int kInplaceCap = (MODE == MODE_F32) ? 7 : 6;
+template <int MODE>
+constexpr int kInplace64Occ = (160 * 1024) / InplaceCfg64<MODE>::LDS_BYTES > kInplaceCap<MODE>
+                                  ? kInplaceCap<MODE>
+                                  : (160 * 1024) / InplaceCfg64<MODE>::LDS_BYTES;
+// 128 x 128 in-place tiles: 4 waves of 64 x 64, the same 16-deep panels in
+// two 16 KB stages; three workgroups per CU (for the registers of the 16-byte
+// loads on rows of any length, and x3's operand split).  Each panel byte feeds
+// twice the MFMAs of a 64 x 64 tile, which halves the operand reads from L2
+// and beyond.
+template <int MODE>
+using InplaceCfg128 = ICfg<MODE, 128, 128, 16, 2, 2, 2>;
+template <int MODE>
+constexpr int kInplace128Occ = 3;
+
 // Direct-to-LDS buffer load of W bytes per lane (the width is an immediate of
 // the instruction, hence the two spellings).
 template <int W>

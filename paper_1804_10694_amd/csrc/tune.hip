@@ -49,7 +49,7 @@ uint64_t schedule_space_hash()
     for (int i = 0; i < num_schedules(); ++i) {
         const SchedDesc& d = schedule(i);
         mix(d.dtype); mix(d.BM); mix(d.BN); mix(d.BK); mix(d.WGM); mix(d.WGN); mix(d.vec);
-        mix(d.lds_bytes); mix(d.split); mix(d.mfma);
+        mix(d.lds_bytes); mix(d.split); mix(d.mfma); mix(d.inplace);
     }
     return h;
 }

@@ -25,7 +25,7 @@ import csv
 import json
 from collections import OrderedDict, defaultdict
 
-MAIN_KERNELS = ("gemm_kernel", "packed_kernel", "packed_sk_kernel", "scaled_kernel")
+MAIN_KERNELS = ("gemm_kernel", "packed_kernel", "packed_sk_kernel", "scaled_kernel", "inplace_gemm_kernel")
 PACK_KERNELS = ("pack_rows_kernel", "pack_cols_kernel")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 

@@ -390,9 +390,9 @@ def schedule_count():
 
 
 def schedule_info(sid):
-    buf = (ctypes.c_int32 * 10)()
+    buf = (ctypes.c_int32 * 11)()
     _check(lib.tgemm_schedule_info(sid, buf), "tgemm_schedule_info")
-    keys = ("dtype", "BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "split", "mfma")
+    keys = ("dtype", "BM", "BN", "BK", "WGM", "WGN", "vec", "lds_bytes", "split", "mfma", "inplace")
     return dict(zip(keys, list(buf)))
 
 
@@ -411,7 +411,7 @@ def schedule_key(sid):
     i = schedule_info(sid)
     return (f"sched:{i['dtype']}:{i['BM']}x{i['BN']}x{i['BK']}:{i['WGM']}x{i['WGN']}:"
             f"vec{i['vec']}:lds{i['lds_bytes']}" + (":streamk" if i["split"] else "")
-            + (":mfma16" if i["mfma"] == 16 else ""))
+            + (":mfma16" if i["mfma"] == 16 else "") + (":inplace" if i["inplace"] else ""))
 
 
 def tile_map(M, N, BM, BN, group_m, xcd_remap):

@@ -110,6 +110,42 @@ def test_packed_schedules_exact_with_vector_packing(tg, dtype):
                                           err_msg=f"schedule {sid} {info} {(M, N, K)}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "x3"])
+def test_inplace_schedules_exact_off_alignment(tg, dtype):
+    # In-place schedules load 16 bytes at any 4-byte aligned address: operands are views
+    # one float into NaN-filled buffers (bases and rows off 16-byte alignment), K and N
+    # off a multiple of 4 (the tail units switch to 4-byte loads), ragged M and N over
+    # several tiles, both tile orders; the NaNs around the operands must never be read.
+    for (M, N, K) in [(300, 270, 37), (200, 130, 129), (129, 67, 300)]:
+        A, B, C0 = inputs.integer_inputs(M, N, K, seed=60 + K)
+        ref = oracle.gemm(A, B, C0, 1.0, 0.5)
+        Ab = torch.full((M + 1, K + 5), float("nan"))
+        Bb = torch.full((K + 1, N + 3), float("nan"))
+        Ab[1:, 1:K + 1] = A
+        Bb[1:, 1:N + 1] = B
+        Ad, Bd = Ab.to(DEV), Bb.to(DEV)
+        a, b = Ad[1:, 1:K + 1], Bd[1:, 1:N + 1]
+        for sid, info in _serving(tg, dtype):
+            if not info["inplace"]:
+                continue
+            for gm, xcd in [(8, 0), (1, 1)]:
+                print(f"in-place schedule {sid} {info} {(M, N, K)} gm={gm} xcd={xcd}", flush=True)
+                c = C0.clone().to(DEV)
+                tg.gemm_with_schedule(a, b, c, 1.0, 0.5, dtype, sid, gm, xcd)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(c.cpu().numpy().astype(np.float64), ref,
+                                              err_msg=f"schedule {sid} {info} {(M, N, K)}")
+
+
+def test_rule_takes_inplace_tiles_for_mid_size_f32(tg):
+    # The built-in rule's f32 choice between packed, stream-K and in-place tiles
+    inplace = lambda M, N, K: tg.schedule_info(tg.select_schedule(M, N, K, "f32")[0])["inplace"]  # noqa: E731
+    assert inplace(4097, 3001, 2053) and inplace(3000, 3000, 3000) and inplace(700, 700, 700)
+    assert not inplace(8192, 8192, 8192)          # 2048 tiles of 128 x 256: packed
+    assert not inplace(1000, 1000, 8192)          # deep K, few tiles: stream-K
+    assert not inplace(512, 512, 512) and not inplace(100, 4096, 4096)
+
+
 @pytest.mark.parametrize("dtype,K", [("f32", 1024), ("x3", 2048)])
 def test_packed_schedules_exact_padded_row_pitch(tg, dtype, K):
     # K * element size a multiple of 4 KB: the packed rows get 512 bytes of padding past K,

@@ -52,14 +52,16 @@ def _call(tg, fn, A, B, C, alpha, beta, dt):
               tg.DTYPES[dt], stream)
 
 
-# (first problem, second smaller problem): both take packed schedules of the rule
-SIZES = [((2048, 2048, 1024), (2000, 1600, 600)), ((3000, 2500, 1100), (1700, 1900, 513))]
+# (first problem, second smaller problem): both take packed schedules of the rule (f32
+# takes them from 1536 tiles of 128 x 256 up; below, in-place tiles that need no workspace)
+SIZES = {"x3": [((2048, 2048, 1024), (2000, 1600, 600)), ((3000, 2500, 1100), (1700, 1900, 513))],
+         "f32": [((8192, 8192, 640), (8192, 6144, 520)), ((8192, 8192, 520), (6144, 8192, 600))]}
 
 
-@pytest.mark.parametrize("sizes", SIZES, ids=["2048^2x1024+2000x1600x600", "3000x2500x1100+1700x1900x513"])
+@pytest.mark.parametrize("case", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "x3"])
-def test_noalloc_matches_tgemm_two_calls(tg, dt, sizes):
-    for n, (M, N, K) in enumerate(sizes):
+def test_noalloc_matches_tgemm_two_calls(tg, dt, case):
+    for n, (M, N, K) in enumerate(SIZES[dt][case]):
         print(f"noalloc {dt} call {n}: {M}x{N}x{K}", flush=True)
         sid, gm, xcd = tg.select_schedule(M, N, K, dt)
         assert tg.schedule_info(sid)["vec"] == 0, "the case must take a packed schedule"
@@ -73,9 +75,11 @@ def test_noalloc_matches_tgemm_two_calls(tg, dt, sizes):
         assert torch.equal(Cn, Cw)
         if tg.schedule_info(sid)["split"] == 0:
             assert torch.equal(Cn, Ct)
-        ref = oracle.gemm(A, B, C0, 1.0, 0.5)
+        # the oracle on 48 sampled rows (the f32 problems are too large for it whole)
+        rows = torch.from_numpy(np.sort(np.random.default_rng(7 + n).choice(M, 48, replace=False)))
+        ref = oracle.gemm(A[rows], B, C0[rows], 1.0, 0.5)
         for out in (Cn, Ct):
-            err = oracle.normwise_error(out.cpu().numpy(), ref)
+            err = oracle.normwise_error(out[rows.to(DEV)].cpu().numpy(), ref)
             assert err <= 1e-5, err
 
 
