@@ -144,7 +144,10 @@ def _summary(ratios):
 
 
 def evaluate(db_path, held_shapes, train_shapes, dtype):
-    """Ratios t_best / t_chosen on the held-out shapes for the three selectors."""
+    """Ratios t_best / t_chosen on the held-out shapes for four selectors: the
+    model, the built-in rule ("default"), the best candidate of the nearest
+    training shape, and one candidate for every shape ("single": the one with
+    the best geometric mean over the training shapes that it serves all of)."""
     tg = _tg()
     code = tg.DTYPES[dtype]
     table = by_shape(read_db(db_path), code)
@@ -153,9 +156,14 @@ def evaluate(db_path, held_shapes, train_shapes, dtype):
     for s in train_shapes:
         if s in table:
             train_best[s] = min(table[s], key=table[s].get)
+    single = None
+    if train_best:
+        common = set.intersection(*(set(table[s]) for s in train_best))
+        score = {c: sum(math.log(min(table[s].values()) / table[s][c]) for s in train_best) for c in common}
+        single = max(score, key=score.get) if score else None
     tlog = np.array([[math.log2(x) for x in s] for s in train_best]) if train_best else None
     tkeys = list(train_best)
-    ratios = {"model": [], "default": [], "nearest": []}
+    ratios = {"model": [], "default": [], "nearest": [], "single": []}
     picks = []
     t_select = []
     for s in held_shapes:
@@ -174,6 +182,8 @@ def evaluate(db_path, held_shapes, train_shapes, dtype):
             q = np.array([math.log2(x) for x in s])
             near = tkeys[int(np.argmin(np.sum((tlog - q) ** 2, axis=1)))]
             choices["nearest"] = train_best[near]
+        if single is not None:
+            choices["single"] = single
         for name, c in choices.items():
             t = meas.get(tuple(c))
             if t is not None:

@@ -1,6 +1,8 @@
 // Schedule selection policies and the tuning database reader.
 #include "select.h"
 
+#include <algorithm>
+
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -196,28 +198,40 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    at least 8 K panels per workgroup of the stream-K wave and enough
     //    tiles (16 and 8) that few workgroups share one.
     const bool narrow = (dtype == TGEMM_F32 || dtype == TGEMM_F32_BF16X3) && (M <= 128 || N <= 128);
-    // f32 below the size of the large packed tiles (under 1536 tiles of
-    // 128 x 256) takes in-place tiles when they give enough workgroups: at
-    // least 1000 tiles of 64 x 64, or 100 with K <= 2048 (deeper problems with
-    // few tiles keep stream-K, which spreads K over every CU).  No packing
-    // pass, and seven (64 x 64) or three (128 x 128) workgroups per CU; 128 x
-    // 128 when its tiles fill at least 60% of their waves of 768.  Measured on
-    // MI355X over 24 shapes in [256, 8192]: f32 against the best of the
-    // previous rule and the four in-place forms, geometric mean 0.857 -> 0.955
-    // (4097 x 3001 x 2053: 0.57 -> 0.47 ms; 4096^3 1.15 -> 1.00; 3000^3 0.61 ->
-    // 0.51; 5000^3 even; 8192^3 keeps the packed tiles).  x3 keeps its packed
-    // and direct tiles, which beat the in-place ones on 22 of those shapes.
-    if (dtype == TGEMM_F32 && !narrow && tiles(128, 256) < 1536 &&
-        (tiles(64, 64) >= 1000 || (K <= 2048 && tiles(64, 64) >= 100))) {
+    // f32 takes in-place tiles except on large squarish problems (at least
+    // 2048 tiles of 128 x 256 and M, N > 512), which keep the packed 128 x 256
+    // tiles: no packing pass, seven (64 x 64) or three (128 x 128) workgroups
+    // per CU; 128 x 128 when its tiles fill at least 60% of their waves of 768
+    // workgroups and M, N >= 256.  Over the 2080 shapes of the cost-model study
+    // (exhaustively tuned on MI355X, every schedule and tile order), the best
+    // schedule was an in-place one for 1876; this rule reaches a geometric
+    // mean of 0.977 of the exhaustive optimum there, against 0.849 for the
+    // rule with the in-place tiles only above 1000 tiles of 64 x 64 and 0.787
+    // without them (4097 x 3001 x 2053: 0.57 -> 0.44 ms; the stream-K form
+    // stays ahead only for deep K on few tiles, e.g. 1000^2 x 8192 by 6%).
+    if (dtype == TGEMM_F32 && (tiles(128, 256) < 2048 || std::min(M, N) <= 512)) {
         const int64_t t = tiles(128, 128);
         const double f = (double)t / (double)(((t + 767) / 768) * 768);
-        const int id = f >= 0.6 ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
-                                : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
-        if (id >= 0) {
-            out->id = id;
-            out->group_m = 8;
-            out->xcd_remap = 0;
-            return TGEMM_SUCCESS;
+        const int id = (f >= 0.6 && std::min(M, N) >= 256) ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
+                                                            : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
+        if (id >= 0) return take(id);
+    }
+    // x3 takes in-place tiles below 768 tiles of 64 x 64 or with K < 1024
+    // (above, the packing pass that splits each operand once is worth its
+    // cost: 4097 x 3001 x 2053 0.175 ms packed against 0.257 in place), 128 x
+    // 128 from 1024 tiles of 64 x 64; problems of whole 64 x 64 tiles with
+    // 16-byte loads and M, N in [512, 4096] keep the direct tiles (1024^3:
+    // 0.025 against 0.034 ms).  Over the study's 2080 shapes the fastest x3
+    // schedule was an in-place one for 1677; this rule reaches 0.959 of the
+    // exhaustive optimum there, against 0.828 without the in-place tiles.
+    if (dtype == TGEMM_F32_BF16X3) {
+        const int64_t t64 = tiles(64, 64);
+        const bool whole = vec_allowed && M % 64 == 0 && N % 64 == 0 && std::min(M, N) >= 512 &&
+                           std::max(M, N) <= 4096;
+        if ((t64 < 768 || K < 1024) && !whole) {
+            const int id = t64 >= 1024 ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
+                                       : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
+            if (id >= 0) return take(id);
         }
     }
     if (K >= 512 && packed_k_ok(K, dtype) && !narrow) {

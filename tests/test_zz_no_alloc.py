@@ -53,9 +53,10 @@ def _call(tg, fn, A, B, C, alpha, beta, dt):
 
 
 # (first problem, second smaller problem): both take packed schedules of the rule (f32
-# takes them from 1536 tiles of 128 x 256 up; below, in-place tiles that need no workspace)
-SIZES = {"x3": [((2048, 2048, 1024), (2000, 1600, 600)), ((3000, 2500, 1100), (1700, 1900, 513))],
-         "f32": [((8192, 8192, 640), (8192, 6144, 520)), ((8192, 8192, 520), (6144, 8192, 600))]}
+# takes them from 2048 tiles of 128 x 256 with M, N > 512, x3 from 768 tiles of 64 x 64 with
+# K >= 1024; otherwise in-place tiles, which need no workspace)
+SIZES = {"x3": [((2048, 2048, 1024), (2000, 1600, 1100)), ((3000, 2500, 1100), (1700, 1900, 1030))],
+         "f32": [((8448, 8192, 640), (8192, 8192, 520)), ((8192, 8448, 600), (8192, 8192, 512))]}
 
 
 @pytest.mark.parametrize("case", [0, 1])
