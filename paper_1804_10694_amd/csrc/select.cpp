@@ -200,9 +200,9 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     const bool narrow = (dtype == TGEMM_F32 || dtype == TGEMM_F32_BF16X3) && (M <= 128 || N <= 128);
     // f32 takes in-place tiles except on large squarish problems (at least
     // 2048 tiles of 128 x 256 and M, N > 512), which keep the packed 128 x 256
-    // tiles: no packing pass, seven (64 x 64) or three (128 x 128) workgroups
-    // per CU; 128 x 128 when its tiles fill at least 60% of their waves of 768
-    // workgroups and M, N >= 256.  Over the 2080 shapes of the cost-model study
+    // tiles: no packing pass, eight (64 x 64) or four (128 x 128) workgroups
+    // per CU; 128 x 128 when its tiles fill at least 60% of waves of 768
+    // workgroups (a threshold set by measurement) and M, N >= 256.  Over the 2080 shapes of the cost-model study
     // (exhaustively tuned on MI355X, every schedule and tile order), the best
     // schedule was an in-place one for 1876; this rule reaches a geometric
     // mean of 0.977 of the exhaustive optimum there, against 0.849 for the

@@ -87,8 +87,11 @@ constexpr int kInplace64Occ = (160 * 1024) / InplaceCfg64<MODE>::LDS_BYTES > kIn
                                   ? kInplaceCap<MODE>
                                   : (160 * 1024) / InplaceCfg64<MODE>::LDS_BYTES;
 // 128 x 128 in-place tiles: 4 waves of 64 x 64, the same 16-deep panels in
-// two 16 KB stages; three workgroups per CU (for the registers of the 16-byte
-// loads on rows of any length, and x3's operand split).  Each panel byte feeds
+// two 16 KB stages; three workgroups per CU in the grouped launch (for the
+// registers of the 16-byte loads on rows of any length, and x3's operand
+// split).  The one-problem kernels (gemm_inplace.hip) have no tile loop and
+// need fewer registers: eight workgroups per CU on 64 x 64 tiles, four (f32)
+// and three (x3) on 128 x 128.  Each panel byte feeds
 // twice the MFMAs of a 64 x 64 tile, which halves the operand reads from L2
 // and beyond.
 template <int MODE>
