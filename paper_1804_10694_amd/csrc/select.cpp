@@ -216,21 +216,24 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
                                                             : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
         if (id >= 0) return take(id);
     }
-    // x3 takes in-place tiles below 768 tiles of 64 x 64 or with K < 1024
-    // (above, the packing pass that splits each operand once is worth its
-    // cost: 4097 x 3001 x 2053 0.175 ms packed against 0.257 in place), 128 x
-    // 128 from 1024 tiles of 64 x 64; problems of whole 64 x 64 tiles with
-    // 16-byte loads and M, N in [512, 4096] keep the direct tiles (1024^3:
-    // 0.025 against 0.034 ms).  Over the study's 2080 shapes the fastest x3
-    // schedule was an in-place one for 1677; this rule reaches 0.959 of the
-    // exhaustive optimum there, against 0.828 without the in-place tiles.
+    // x3 takes in-place tiles below 768 tiles of 64 x 64, with K < 1024 or
+    // with M or N <= 512 (above all that, the packing pass that splits each
+    // operand once is worth its cost: 4097 x 3001 x 2053 0.175 ms packed
+    // against 0.257 in place), 128 x 128 from 1024 tiles of 64 x 64; M or N
+    // <= 64 take the direct 64 x 64 tiles instead, and problems of whole
+    // 64 x 64 tiles with 16-byte loads and M, N in [512, 4096] keep the
+    // direct tiles (1024^3: 0.025 against 0.034 ms).  Over the study's 2080
+    // shapes the fastest x3 schedule was an in-place one for 1677; this rule
+    // reaches 0.967 of the exhaustive optimum there (0.948 on its 80 im2col
+    // shapes of 3x3 convolutions), against 0.828 without the in-place tiles.
     if (dtype == TGEMM_F32_BF16X3) {
         const int64_t t64 = tiles(64, 64);
         const bool whole = vec_allowed && M % 64 == 0 && N % 64 == 0 && std::min(M, N) >= 512 &&
                            std::max(M, N) <= 4096;
-        if ((t64 < 768 || K < 1024) && !whole) {
-            const int id = t64 >= 1024 ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
-                                       : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
+        if ((t64 < 768 || K < 1024 || std::min(M, N) <= 512) && !whole) {
+            const int id = std::min(M, N) <= 64 ? find_schedule(dtype, 64, 64, 32, vec_allowed ? 4 : 1)
+                           : t64 >= 1024       ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)
+                                               : find_schedule(dtype, 64, 64, 16, 1, 2, 2, -1, 32, 0, 1);
             if (id >= 0) return take(id);
         }
     }
