@@ -137,15 +137,6 @@ def test_inplace_schedules_exact_off_alignment(tg, dtype):
                                               err_msg=f"schedule {sid} {info} {(M, N, K)}")
 
 
-def test_rule_takes_inplace_tiles_for_mid_size_f32(tg):
-    # The built-in rule's f32 choice between packed, stream-K and in-place tiles
-    inplace = lambda M, N, K: tg.schedule_info(tg.select_schedule(M, N, K, "f32")[0])["inplace"]  # noqa: E731
-    assert inplace(4097, 3001, 2053) and inplace(3000, 3000, 3000) and inplace(700, 700, 700)
-    assert inplace(1000, 1000, 8192) and inplace(100, 4096, 4096) and inplace(8192, 512, 8192)
-    assert not inplace(8192, 8192, 8192)          # 2048 tiles of 128 x 256: packed
-    assert not inplace(8192, 8192, 512)
-
-
 @pytest.mark.parametrize("dtype,K", [("f32", 1024), ("x3", 2048)])
 def test_packed_schedules_exact_padded_row_pitch(tg, dtype, K):
     # K * element size a multiple of 4 KB: the packed rows get 512 bytes of padding past K,
