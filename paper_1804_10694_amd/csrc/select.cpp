@@ -202,9 +202,10 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     // 2048 tiles of 128 x 256 and M, N > 512), which keep the packed 128 x 256
     // tiles: no packing pass, eight (64 x 64) or four (128 x 128) workgroups
     // per CU; 128 x 128 when its tiles fill at least 60% of waves of 768
-    // workgroups (a threshold set by measurement) and M, N >= 256.  Over the 2080 shapes of the cost-model study
-    // (exhaustively tuned on MI355X, every schedule and tile order), the best
-    // schedule was an in-place one for 1876; this rule reaches a geometric
+    // workgroups (a threshold set by measurement) and M, N >= 256.  Over the
+    // 2080 shapes of the cost-model study (exhaustively tuned on MI355X, every
+    // schedule and tile order), the best schedule was an in-place one for
+    // 1876; this rule reaches a geometric
     // mean of 0.977 of the exhaustive optimum there, against 0.849 for the
     // rule with the in-place tiles only above 1000 tiles of 64 x 64 and 0.787
     // without them (4097 x 3001 x 2053: 0.57 -> 0.44 ms; the stream-K form
