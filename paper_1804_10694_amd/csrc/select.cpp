@@ -198,6 +198,16 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     //    at least 8 K panels per workgroup of the stream-K wave and enough
     //    tiles (16 and 8) that few workgroups share one.
     const bool narrow = (dtype == TGEMM_F32 || dtype == TGEMM_F32_BF16X3) && (M <= 128 || N <= 128);
+    // Deep K on few tiles (K >= 4096, under 768 tiles of 64 x 64, M and N at
+    // least 256), f32 and x3 alike: stream-K, which spreads K over every CU
+    // (f32 1000^2 x 8192 0.234 ms against 0.248 in place; x3 0.136 against
+    // 0.255).
+    const bool deep = K >= 4096 && tiles(64, 64) < 768 && std::min(M, N) >= 256 && packed_k_ok(K, dtype);
+    if (dtype == TGEMM_F32 && deep) {
+        const int sk = tiles(128, 256) >= 16 ? find_schedule(dtype, 128, 256, 16, 0, 4, 2, -1, 32, 1)
+                                             : find_schedule(dtype, 128, 128, 16, 0, 2, 2, -1, 32, 1);
+        if (sk >= 0) return take(sk);
+    }
     // f32 takes in-place tiles except on large squarish problems (at least
     // 2048 tiles of 128 x 256 and M, N > 512), which keep the packed 128 x 256
     // tiles: no packing pass, eight (64 x 64) or four (128 x 128) workgroups
@@ -205,11 +215,10 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     // workgroups (a threshold set by measurement) and M, N >= 256.  Over the
     // 2080 shapes of the cost-model study (exhaustively tuned on MI355X, every
     // schedule and tile order), the best schedule was an in-place one for
-    // 1876; this rule reaches a geometric
-    // mean of 0.977 of the exhaustive optimum there, against 0.849 for the
+    // 1876; this rule (with the deep-K exception) reaches a geometric
+    // mean of 0.978 of the exhaustive optimum there, against 0.849 for the
     // rule with the in-place tiles only above 1000 tiles of 64 x 64 and 0.787
-    // without them (4097 x 3001 x 2053: 0.57 -> 0.44 ms; the stream-K form
-    // stays ahead only for deep K on few tiles, e.g. 1000^2 x 8192 by 6%).
+    // without them (4097 x 3001 x 2053: 0.57 -> 0.44 ms).
     if (dtype == TGEMM_F32 && (tiles(128, 256) < 2048 || std::min(M, N) <= 512)) {
         const int64_t t = tiles(128, 128);
         const double f = (double)t / (double)(((t + 767) / 768) * 768);
@@ -225,12 +234,18 @@ int default_schedule(int64_t M, int64_t N, int64_t K, int dtype, bool vec_allowe
     // 64 x 64 tiles with 16-byte loads and M, N in [512, 4096] keep the
     // direct tiles (1024^3: 0.025 against 0.034 ms).  Over the study's 2080
     // shapes the fastest x3 schedule was an in-place one for 1677; this rule
-    // reaches 0.967 of the exhaustive optimum there (0.948 on its 80 im2col
-    // shapes of 3x3 convolutions), against 0.828 without the in-place tiles.
+    // (with the deep-K exception) reaches 0.973 of the exhaustive optimum
+    // there (0.948 on its 80 im2col shapes of 3x3 convolutions), against 0.828
+    // without the in-place tiles.
     if (dtype == TGEMM_F32_BF16X3) {
         const int64_t t64 = tiles(64, 64);
         const bool whole = vec_allowed && M % 64 == 0 && N % 64 == 0 && std::min(M, N) >= 512 &&
                            std::max(M, N) <= 4096;
+        if (deep) {
+            const int sk = tiles(256, 256) >= 8 ? find_schedule(dtype, 256, 256, 32, 0, 2, 4, -1, 32, 1)
+                                                : find_schedule(dtype, 128, 128, 16, 0, 2, 2, -1, 32, 1);
+            if (sk >= 0) return take(sk);
+        }
         if ((t64 < 768 || K < 1024 || std::min(M, N) <= 512) && !whole) {
             const int id = std::min(M, N) <= 64 ? find_schedule(dtype, 64, 64, 32, vec_allowed ? 4 : 1)
                            : t64 >= 1024       ? find_schedule(dtype, 128, 128, 16, 1, 2, 2, -1, 32, 0, 1)

@@ -26,7 +26,9 @@ def _kind(tg, M, N, K, dt):
     ((4097, 3001, 2053), "inplace64"),     # 128 x 128 tiles would fill half of their second wave
     ((4096, 4096, 4096), "inplace128"),
     ((700, 700, 700), "inplace64"),
-    ((1000, 1000, 8192), "inplace64"),     # deep K, few tiles: still in place (stream-K is 6% ahead)
+    ((1000, 1000, 8192), "streamk"),       # deep K on few tiles: stream-K spreads K over every CU
+    ((256, 256, 8192), "streamk"),
+    ((200, 4000, 8192), "inplace64"),      # M < 256: in place even with deep K
     ((100, 4096, 4096), "inplace64"),      # narrow
     ((401408, 64, 1152), "inplace64"),     # im2col of a 3x3 convolution, 64 output channels
     ((8192, 512, 8192), "inplace64"),      # M or N <= 512: in place at any size
@@ -42,6 +44,7 @@ def test_f32_rule(tg, shape, kind):
     ((8192, 8192, 8192), "packed"),
     ((2048, 2048, 1024), "packed"),
     ((300, 5000, 2000), "inplace64"),      # M <= 512
+    ((1000, 1000, 8192), "streamk"),       # deep K on few tiles
     ((700, 700, 700), "inplace64"),        # 121 tiles
     ((6000, 2000, 700), "inplace128"),     # K < 1024, 2945 tiles
     ((100352, 256, 2304), "inplace128"),   # im2col, N <= 512
